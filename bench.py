@@ -1,0 +1,137 @@
+"""Benchmark of the PDMCF hot path on one MI355X.
+
+A step is one full solve from the cold start to the stopping tolerance: every
+PDHG iteration (edge phase, node phase, FP64 control) plus the residual/KKT
+check every `check_every` iterations, with the instance already resident in
+HBM.  Default workload: n = 200 ring + chords with out-degree 10 (m = 2000),
+capacities U[0.5, 2], log utility with w ~ U[0.5, 1.5], FP32 iterates with FP64
+reductions, relative KKT tolerance 1e-4.
+
+Prints one JSON line with the throughput in edge-dest updates per second
+(n * m * iterations / second), the roofline of the dominant (edge-phase) kernel
+measured with HIP events inside the timed region, and the CPU oracle timed on
+a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def workload(name: str):
+    from paper_2501_17996_amd import instances as I
+    if name == "c2":
+        return I.config2(0), 1e-4, ("n=200 ring+chords out-degree 10 (m=2000), c~U[0.5,2], log utility "
+                                    "w~U[0.5,1.5], solve to rel KKT 1e-4")
+    if name == "c3":
+        return I.config3(0), 1e-4, ("n=1000 ring+chords out-degree 10 (m=10000), c~lognormal(0,0.5), "
+                                    "power utility gamma=0.5, solve to rel KKT 1e-4")
+    if name == "c4":
+        return I.config4(0), 1e-3, ("n=10000 ring+chords out-degree 10 (m=100000), c~U[0.5,2], log utility, "
+                                    "solve to rel KKT 1e-3")
+    raise SystemExit(f"unknown workload {name}")
+
+
+def edge_alg_bytes(n: int, m: int, s: int, check: bool) -> float:
+    """Algorithmic bytes of one edge-phase launch: read F, write F and Fbar
+    (3 s n m) and read every column of Y once (s n^2); a check launch also
+    writes Fhat and D (2 s n m)."""
+    return s * (3.0 * n * m + n * n + (2.0 * n * m if check else 0.0))
+
+
+def cpu_baseline(inst, tol, check_every, budget_s: float):
+    import oracle
+    threads = max(1, min(16, os.cpu_count() or 1))
+    O = oracle.OracleSolver(inst, threads=threads)
+    iters, t0 = 0, time.perf_counter()
+    while time.perf_counter() - t0 < budget_s:
+        for _ in range(check_every):
+            O.step(check=(_ == check_every - 1))
+        iters += check_every
+    dt = time.perf_counter() - t0
+    return {"value": inst.n * inst.m * iters / dt, "unit": "edge-dest updates/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{iters} PDHG iterations of the same instance from the cold start (residual every "
+                      f"{check_every}), FP64, {dt:.1f} s on {threads} threads"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--check-every", type=int, default=10)
+    ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        raise SystemExit(2)
+
+    import torch
+    from paper_2501_17996_amd import mcf
+
+    torch.cuda.set_device(0)
+    inst, tol, desc = workload(args.workload)
+    prec = mcf.MCF_FP32 if args.precision == "fp32" else mcf.MCF_FP64
+    s = 4 if prec == mcf.MCF_FP32 else 8
+    stream = torch.cuda.current_stream()
+    S = mcf.Solver(inst, precision=prec, tol=tol, check_every=args.check_every, max_iter=200000,
+                   stream=stream.cuda_stream)
+    for _ in range(args.warmup):
+        S.reset()
+        S.solve()
+    torch.cuda.synchronize()
+    mcf.mcf_enable_kernel_timing(S.h, True)
+    iters = 0
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        S.reset()
+        st = S.solve()
+        iters += st["iters"]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    edge_ms, launches = mcf.mcf_kernel_time(S.h)
+    mcf.mcf_enable_kernel_timing(S.h, False)
+    n, m = inst.n, inst.m
+    checks = launches // args.check_every if args.check_every > 0 else 0
+    alg = edge_alg_bytes(n, m, s, False) * (launches - checks) + edge_alg_bytes(n, m, s, True) * checks
+    achieved = alg / (edge_ms * 1e-3) / 1e9 if edge_ms > 0 else 0.0
+    value = n * m * iters / dt
+    out = {
+        "metric": "PDHG edge-dest updates/s (n*m*iters/s)",
+        "value": value,
+        "unit": "edge-dest updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if prec == mcf.MCF_FP32 else "f64",
+        "data": "synthetic",
+        "config": {"workload": desc, "n": n, "m": m, "precision": args.precision,
+                   "reductions": "f64", "check_every": args.check_every, "tol": tol,
+                   "iters_per_solve": iters / args.steps, "final_rel_kkt": st["rel_kkt"],
+                   "time_to_tol_ms": dt / args.steps * 1e3},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "edge phase", "avg_launch_us": edge_ms * 1e3 / max(1, launches),
+                     "launches": launches},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(inst, tol, args.check_every, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

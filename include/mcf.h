@@ -1,0 +1,157 @@
+/*
+ * mcf.h -- C ABI of libmcf, an MI355X (gfx950) PDHG solver for the
+ * destination-aggregated all-pairs multicommodity network flow problem
+ * (Zhang & Boyd, "Solving Large Multicommodity Network Flow Problems on GPUs",
+ * arXiv 2501.17996).
+ *
+ * Problem (Section 1.1, (e-prob)/(e-compact-prob)): maximize U(T) = sum_{i!=j} u_ij(T_ij)
+ * over the destination-based flow F (n x m, F_il = flow on edge l destined to node i)
+ * subject to F >= 0, F^T 1 <= c and T = -F A^T, where A is the incidence matrix
+ * (A[head(l), l] = +1, A[tail(l), l] = -1) and T_ij is the traffic from j to i.
+ * Method: Algorithm 2.1 (PDMCF): the over-relaxed PDHG step (e-pdhg-step), the
+ * projection onto {f >= 0, 1^T f <= c_l} per edge column (Section 2.3), the dual
+ * proximal operators of the log and power utilities (Section 2.3), the adaptive
+ * primal weight (e-primal_weight) and eta = 1/sqrt(2 d_max) (e-eta).
+ *
+ * Conventions for every function:
+ *   - every call returns int: MCF_OK (0) or a negative MCF_E_* code; nothing
+ *     throws or aborts; mcf_strerror() names a code;
+ *   - host arrays are plain host pointers; the library copies what it needs, so
+ *     callers may free inputs on return;
+ *   - device memory belongs to the handle, or lives inside the caller's workspace
+ *     (mcf_options.workspace, e.g. a torch tensor's data pointer) when one is given;
+ *   - a handle is used by one host thread at a time; handles are independent.
+ *
+ * Layouts (host side, always FP64 even when the iterates are FP32):
+ *   F: n*m, F[l*n + i] = flow on user edge l destined to node i;
+ *   T, Y, w: n*n, X[j*n + i] = entry (i, j); w[j*n+i] weights the traffic j -> i.
+ */
+#ifndef MCF_H
+#define MCF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mcf_solver mcf_solver; /* opaque; owns its device buffers */
+
+enum { MCF_UTIL_LOG = 0, MCF_UTIL_POWER = 1 };            /* u = w log s  |  u = w s^gamma (Section 1.1) */
+enum { MCF_FP64 = 0, MCF_FP32 = 1 };                     /* precision of F, Y; reductions are always FP64 */
+enum { MCF_STOP_REL_KKT = 0, MCF_STOP_PAPER = 1 };       /* rel_kkt <= tol  |  r^k < n m tol (Algorithm 2.1) */
+enum { MCF_OK = 0, MCF_E_ARG = -1, MCF_E_GRAPH = -2, MCF_E_NOMEM = -3, MCF_E_DEVICE = -4, MCF_E_STATE = -5 };
+enum { MCF_RUNNING = 0, MCF_CONVERGED = 1, MCF_MAX_ITER = 2, MCF_DIVERGED = 3 }; /* solve states, not errors */
+
+/* Solver options.  Defaults (mcf_options_default) are the paper's parameters:
+ * rho = 1.9 (Section 2.2), theta = 0.5, k_adapt = 100, tau = 1e-5, omega0 = 1 (Section 2.4). */
+typedef struct {
+    double tol;             /* stopping tolerance, > 0 (meaning set by stop_rule) */
+    int64_t max_iter;       /* iteration limit (total, counted from the cold start) */
+    int32_t precision;      /* MCF_FP64 or MCF_FP32 */
+    int32_t stop_rule;      /* MCF_STOP_REL_KKT or MCF_STOP_PAPER */
+    int32_t check_every;    /* residual evaluated every check_every iterations (>= 1) and at the last one */
+    int32_t k_adapt;        /* adapt omega when k is a multiple of k_adapt (k = 0 included); <= 0 disables */
+    double rho, theta, tau, omega0;
+    int32_t device;         /* HIP device ordinal */
+    int32_t reserved0;
+    void *stream;           /* hipStream_t to run on, or NULL for a stream owned by the handle */
+    void *workspace;        /* optional caller device memory (>= mcf_workspace_bytes), or NULL */
+    size_t workspace_bytes;
+} mcf_options;
+
+/* Latest solve record.  Residuals are those of the last checked iteration:
+ *   r          the residual r(Q^k) of (e-res) (+inf while T^ is not positive off the diagonal);
+ *   r_paper    r / (n m), compared with tol by MCF_STOP_PAPER;
+ *   rel_primal ||offdiag(T(Y^k) - T^)||_F / ||offdiag T^||_F, T(Y) the traffic the prices Y ask for;
+ *   rel_dual   sqrt(r / ||G||_F^2) with G = U'A;
+ *   rel_gap    (p - d) / (1 + |p| + |d|), p = -U(T^), d the dual objective of the reduced Lagrangian (e-L);
+ *   rel_kkt    max(rel_primal, rel_dual, rel_gap), +inf unless T^ > 0 and Y^k < 0 off the diagonal. */
+typedef struct {
+    int32_t state;          /* MCF_RUNNING / CONVERGED / MAX_ITER / DIVERGED */
+    int32_t checked;        /* 1 if the residual fields belong to the last iteration */
+    int64_t iters;          /* PDHG iterations performed since the cold start */
+    double r, r_paper, rel_primal, rel_dual, rel_gap, rel_kkt;
+    double primal_obj, dual_obj, infeasible_frac;
+    double omega, alpha, beta, delta_f, delta_y;
+    double seconds;         /* wall time of the last mcf_solve / mcf_run call */
+} mcf_result;
+
+/* Resumable scalar state (Section 2.5 warm start): iteration k and primal weight omega. */
+typedef struct {
+    int64_t k;
+    double omega;
+} mcf_scalars;
+
+/* Fills *o with the defaults: tol 1e-4, REL_KKT, FP64, check_every 1, max_iter 100000,
+ * k_adapt 100, rho 1.9, theta 0.5, tau 1e-5, omega0 1, device 0, no stream, no workspace. */
+void mcf_options_default(mcf_options *o);
+
+/* Device bytes one instance needs at this precision (buffers, CSR lists, partials).
+ * Returns 0 if n or m is out of range. */
+size_t mcf_workspace_bytes(int32_t n, int32_t m, int32_t precision);
+
+/* Builds an instance and sets the cold start of Section 2.5 (F = 0, Y = I - 1 1^T, omega = omega0).
+ *   n, m       nodes (2 <= n <= 32768) and edges (m >= 1);
+ *   tail, head m edge endpoints in [0, n), tail != head (parallel edges allowed);
+ *   cap        m capacities c_l > 0 (Section 1.1);
+ *   utility    MCF_UTIL_LOG or MCF_UTIL_POWER; gamma in (0, 1) for POWER (ignored for LOG);
+ *   w          n*n weights, w[j*n+i] > 0 for i != j (diagonal ignored);
+ *   opt        options or NULL for the defaults.
+ * Errors: MCF_E_ARG for any range/positivity/NULL violation or tol <= 0; MCF_E_GRAPH if the
+ * graph is not strongly connected (Section 1.1 requires a path between every pair);
+ * MCF_E_NOMEM / MCF_E_DEVICE for allocation or HIP failures.  *out is NULL on error. */
+int mcf_create(int32_t n, int32_t m, const int32_t *tail, const int32_t *head, const double *cap,
+               int32_t utility, double gamma, const double *w, const mcf_options *opt, mcf_solver **out);
+
+/* Runs Algorithm 2.1 from the current state until the stop rule holds, the iteration
+ * count reaches max_iter, or the step norms become non-finite.  Blocking.  Returns MCF_OK
+ * whatever the outcome: read the outcome with mcf_status. */
+int mcf_solve(mcf_solver *s);
+
+/* Runs exactly `iters` more PDHG iterations with no stop test (residual every check_every
+ * iterations and at the last one).  For trajectory comparison and timing. */
+int mcf_run(mcf_solver *s, int64_t iters);
+
+/* Restores the cold start (F = 0, Y = I - 1 1^T, omega = omega0, k = 0) on the device. */
+int mcf_reset(mcf_solver *s);
+
+/* Copies the latest record into *out. */
+int mcf_status(const mcf_solver *s, mcf_result *out);
+
+/* Downloads the projected flow Fhat of the last checked iteration (the iterate Algorithm 2.1
+ * returns), its traffic T = -Fhat A^T, and the current dual Y.  NULL outputs are skipped. */
+int mcf_get_solution(mcf_solver *s, double *F, double *T, double *Y);
+
+/* Downloads the resumable state: F^{k-1/2}, Y^k and the scalars.  NULL outputs are skipped. */
+int mcf_get_state(mcf_solver *s, double *F, double *Y, mcf_scalars *sc);
+
+/* Uploads a state (warm start or resume).  F may not be NULL; Y and sc may be NULL to keep
+ * the current ones.  Values are rounded to the iterate precision. */
+int mcf_set_state(mcf_solver *s, const double *F, const double *Y, const mcf_scalars *sc);
+
+/* Releases the handle and its device memory.  NULL-safe. */
+void mcf_destroy(mcf_solver *s);
+
+/* Static text for a return code. */
+const char *mcf_strerror(int code);
+
+/* Test hook: writes a NaN into F (which = 0, flat user index l*n+i) or Y (which = 1,
+ * j*n+i) on the device; the next iteration then reports MCF_DIVERGED. */
+int mcf_debug_poison(mcf_solver *s, int32_t which, int64_t index);
+
+/* Kernel timing for the roofline of the dominant (edge-phase) kernel: while enabled, HIP
+ * events bracket every edge-phase launch on the solver's stream; mcf_kernel_time returns
+ * the summed milliseconds and the launch count since the last enable. */
+int mcf_enable_kernel_timing(mcf_solver *s, int32_t enable);
+int mcf_kernel_time(mcf_solver *s, double *edge_ms, int64_t *edge_launches);
+
+/* Internal sizes chosen at create: padded leading dimension and threads per edge column. */
+int mcf_layout(const mcf_solver *s, int32_t *ld, int32_t *edge_block, int32_t *edge_ept);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MCF_H */

@@ -1,0 +1,75 @@
+// Internal declarations shared by the libmcf kernels and its host runtime.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mcf {
+
+// Device-resident scalar state of Algorithm 2.1 and the latest check record.
+// The control kernel is the only writer during a solve; the host reads it after
+// each block of iterations and writes it only while the stream is idle.
+struct DevScalars {
+    double omega, alpha, beta, eta;
+    double dF, dY;
+    double r, r_paper, rel_primal, rel_dual, rel_gap, rel_kkt;
+    double primal_obj, dual_obj, infeasible_frac, a, b, e;
+    long long k;
+    int stop;     // 1: every kernel returns at entry (set on convergence or divergence)
+    int state;    // MCF_RUNNING / MCF_CONVERGED / MCF_DIVERGED
+    int checked;  // the check fields belong to the last iteration
+    int stop_enabled;  // 1: a met stop rule raises `stop` (mcf_solve); 0: run on (mcf_run)
+};
+
+// Read-only problem description and constants of one instance.
+struct Consts {
+    int n, m;
+    long long ld;          // padded column length of F, Y, W, T, U'
+    int utility;           // 0 log, 1 power
+    double gamma, c1, rho, theta, tau, tol;
+    int k_adapt, stop_rule;
+    int nblk_node;         // node-phase blocks (partials per quantity)
+};
+
+// Offsets (in doubles) of the partial-sum segments.
+struct PartLayout {
+    long long dF, e, sup, a, b;               // m each (one per edge)
+    long long dY, p, conj, rnum, rden, nonpos, yinf;  // nblk_node each
+    long long total;
+};
+
+template <typename T>
+struct Bufs {
+    T *F, *Fbar, *Fhat, *D, *Y, *W;
+    double *That, *Up;
+    const int *tail, *head, *out_off, *in_off, *in_edge;
+    const double *cap;
+    double *part;
+    DevScalars *sc;
+};
+
+// Per-edge launch shape: BLOCK threads per edge column, EPT entries per thread.
+struct EdgeShape {
+    int block, ept;
+};
+EdgeShape edge_shape_for(int n);
+
+// Kernel launchers (defined in mcf_kernels.hip).
+template <typename T>
+hipError_t launch_init(const Consts &c, const Bufs<T> &b, double omega0, hipStream_t st);
+template <typename T>
+hipError_t launch_edge(const Consts &c, const Bufs<T> &b, const PartLayout &pl, EdgeShape sh, bool check,
+                       hipStream_t st);
+template <typename T>
+hipError_t launch_node(const Consts &c, const Bufs<T> &b, const PartLayout &pl, bool check, hipStream_t st);
+template <typename T>
+hipError_t launch_residual(const Consts &c, const Bufs<T> &b, const PartLayout &pl, EdgeShape sh,
+                           hipStream_t st);
+template <typename T>
+hipError_t launch_control(const Consts &c, const Bufs<T> &b, const PartLayout &pl, bool check, hipStream_t st);
+template <typename T>
+hipError_t launch_poison(const Bufs<T> &b, int which, long long offset, hipStream_t st);
+
+constexpr int NODE_BLOCK = 256;
+
+}  // namespace mcf

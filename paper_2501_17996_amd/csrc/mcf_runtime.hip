@@ -1,0 +1,660 @@
+// libmcf host runtime: instance setup, device buffers, the iteration driver and
+// the C ABI declared in include/mcf.h.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "mcf.h"
+#include "mcf_internal.h"
+
+using namespace mcf;
+
+namespace {
+
+constexpr int MAX_N = 16384;
+constexpr size_t ALIGN = 256;
+
+size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
+
+long long padded_ld(int n) { return (long long)((n + 63) / 64) * 64; }
+
+int node_blocks(int n) { return ((n + NODE_BLOCK - 1) / NODE_BLOCK) * n; }
+
+PartLayout part_layout(int m, int nb)
+{
+    PartLayout p;
+    long long o = 0;
+    p.dF = o; o += m;
+    p.e = o; o += m;
+    p.sup = o; o += m;
+    p.a = o; o += m;
+    p.b = o; o += m;
+    p.dY = o; o += nb;
+    p.p = o; o += nb;
+    p.conj = o; o += nb;
+    p.rnum = o; o += nb;
+    p.rden = o; o += nb;
+    p.nonpos = o; o += nb;
+    p.yinf = o; o += nb;
+    p.total = o;
+    return p;
+}
+
+// Byte offsets of every device buffer inside one allocation.
+struct Plan {
+    size_t F, Fbar, Fhat, D, Y, W, That, Up, cap, tail, head, out_off, in_off, in_edge, part, sc, total;
+};
+
+Plan make_plan(int n, int m, int precision)
+{
+    const size_t es = precision == MCF_FP32 ? 4 : 8;
+    const size_t ld = (size_t)padded_ld(n);
+    const size_t nm = ld * (size_t)m, nn = ld * (size_t)n;
+    const PartLayout pl = part_layout(m, node_blocks(n));
+    Plan p;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes); return at; };
+    p.F = take(nm * es);
+    p.Fbar = take(nm * es);
+    p.Fhat = take(nm * es);
+    p.D = take(nm * es);
+    p.Y = take(nn * es);
+    p.W = take(nn * es);
+    p.That = take(nn * 8);
+    p.Up = take(nn * 8);
+    p.cap = take((size_t)m * 8);
+    p.tail = take((size_t)m * 4);
+    p.head = take((size_t)m * 4);
+    p.out_off = take((size_t)(n + 1) * 4);
+    p.in_off = take((size_t)(n + 1) * 4);
+    p.in_edge = take((size_t)m * 4);
+    p.part = take((size_t)pl.total * 8);
+    p.sc = take(sizeof(DevScalars));
+    p.total = o;
+    return p;
+}
+
+}  // namespace
+
+struct mcf_solver {
+    int n = 0, m = 0, precision = 0;
+    long long ld = 0;
+    mcf_options opt{};
+    Consts c{};
+    PartLayout pl{};
+    EdgeShape sh{};
+    Plan plan{};
+    std::vector<int> perm;  // internal edge -> user edge
+    char *base = nullptr;
+    bool own_mem = false;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    DevScalars *hs = nullptr;  // pinned host mirror of the device scalars
+    int state = MCF_RUNNING;
+    double seconds = 0.0;
+    // kernel timing of the edge phase
+    bool timing = false;
+    std::vector<hipEvent_t> ev;  // pairs (start, stop) of the current block
+    size_t ev_used = 0;
+    double edge_ms = 0.0;
+    long long edge_launches = 0;
+
+    template <typename T>
+    Bufs<T> bufs() const
+    {
+        Bufs<T> b;
+        b.F = (T *)(base + plan.F);
+        b.Fbar = (T *)(base + plan.Fbar);
+        b.Fhat = (T *)(base + plan.Fhat);
+        b.D = (T *)(base + plan.D);
+        b.Y = (T *)(base + plan.Y);
+        b.W = (T *)(base + plan.W);
+        b.That = (double *)(base + plan.That);
+        b.Up = (double *)(base + plan.Up);
+        b.tail = (const int *)(base + plan.tail);
+        b.head = (const int *)(base + plan.head);
+        b.out_off = (const int *)(base + plan.out_off);
+        b.in_off = (const int *)(base + plan.in_off);
+        b.in_edge = (const int *)(base + plan.in_edge);
+        b.cap = (const double *)(base + plan.cap);
+        b.part = (double *)(base + plan.part);
+        b.sc = (DevScalars *)(base + plan.sc);
+        return b;
+    }
+    DevScalars *dsc() const { return (DevScalars *)(base + plan.sc); }
+};
+
+namespace {
+
+int hip_err(hipError_t e) { return e == hipSuccess ? MCF_OK : (e == hipErrorOutOfMemory ? MCF_E_NOMEM : MCF_E_DEVICE); }
+
+#define MCF_TRY(expr)                       \
+    do {                                    \
+        hipError_t _e = (expr);             \
+        if (_e != hipSuccess) return hip_err(_e); \
+    } while (0)
+
+// Strong connectivity (Section 1.1 requires a directed path between every pair):
+// every node is reached from node 0 along edges and along reversed edges.
+bool strongly_connected(int n, int m, const int *tail, const int *head)
+{
+    for (int dir = 0; dir < 2; ++dir) {
+        std::vector<int> off(n + 1, 0), adj(m);
+        const int *from = dir == 0 ? tail : head, *to = dir == 0 ? head : tail;
+        for (int l = 0; l < m; ++l) off[from[l] + 1]++;
+        for (int i = 0; i < n; ++i) off[i + 1] += off[i];
+        std::vector<int> pos(off.begin(), off.end() - 1);
+        for (int l = 0; l < m; ++l) adj[pos[from[l]]++] = to[l];
+        std::vector<char> seen(n, 0);
+        std::vector<int> stack{0};
+        seen[0] = 1;
+        int count = 1;
+        while (!stack.empty()) {
+            int u = stack.back();
+            stack.pop_back();
+            for (int k = off[u]; k < off[u + 1]; ++k)
+                if (!seen[adj[k]]) {
+                    seen[adj[k]] = 1;
+                    ++count;
+                    stack.push_back(adj[k]);
+                }
+        }
+        if (count != n) return false;
+    }
+    return true;
+}
+
+template <typename T>
+int upload_problem(mcf_solver *s, const int *tail, const int *head, const double *cap, const double *w)
+{
+    const int n = s->n, m = s->m;
+    const long long ld = s->ld;
+    // internal edge order: sorted by (tail, head, user index); out-edges of a node are contiguous
+    std::vector<int> &perm = s->perm;
+    perm.resize(m);
+    for (int l = 0; l < m; ++l) perm[l] = l;
+    std::sort(perm.begin(), perm.end(), [&](int a, int b) {
+        if (tail[a] != tail[b]) return tail[a] < tail[b];
+        if (head[a] != head[b]) return head[a] < head[b];
+        return a < b;
+    });
+    std::vector<int> t(m), h(m), out_off(n + 1, 0), in_off(n + 1, 0), in_edge(m);
+    std::vector<double> c(m);
+    for (int e = 0; e < m; ++e) {
+        t[e] = tail[perm[e]];
+        h[e] = head[perm[e]];
+        c[e] = cap[perm[e]];
+        out_off[t[e] + 1]++;
+        in_off[h[e] + 1]++;
+    }
+    for (int i = 0; i < n; ++i) {
+        out_off[i + 1] += out_off[i];
+        in_off[i + 1] += in_off[i];
+    }
+    std::vector<int> pos(in_off.begin(), in_off.end() - 1);
+    for (int e = 0; e < m; ++e) in_edge[pos[h[e]]++] = e;  // ascending internal id within each node
+    // eta = 1/sqrt(2 d_max), d_i = in-degree + out-degree = (A A^T)_ii (e-eta, Appendix A)
+    int dmax = 0;
+    for (int i = 0; i < n; ++i)
+        dmax = std::max(dmax, (out_off[i + 1] - out_off[i]) + (in_off[i + 1] - in_off[i]));
+    const double eta = 1.0 / std::sqrt(2.0 * (double)dmax);
+    // weights, padded columns, iterate precision
+    std::vector<T> W((size_t)ld * n, T(0));
+    for (int j = 0; j < n; ++j)
+        for (int i = 0; i < n; ++i) W[(size_t)j * ld + i] = (i == j) ? T(0) : (T)w[(size_t)j * n + i];
+    char *b = s->base;
+    const Plan &p = s->plan;
+    hipStream_t st = s->stream;
+    MCF_TRY(hipMemcpyAsync(b + p.W, W.data(), W.size() * sizeof(T), hipMemcpyHostToDevice, st));
+    MCF_TRY(hipMemcpyAsync(b + p.cap, c.data(), m * 8, hipMemcpyHostToDevice, st));
+    MCF_TRY(hipMemcpyAsync(b + p.tail, t.data(), m * 4, hipMemcpyHostToDevice, st));
+    MCF_TRY(hipMemcpyAsync(b + p.head, h.data(), m * 4, hipMemcpyHostToDevice, st));
+    MCF_TRY(hipMemcpyAsync(b + p.out_off, out_off.data(), (n + 1) * 4, hipMemcpyHostToDevice, st));
+    MCF_TRY(hipMemcpyAsync(b + p.in_off, in_off.data(), (n + 1) * 4, hipMemcpyHostToDevice, st));
+    MCF_TRY(hipMemcpyAsync(b + p.in_edge, in_edge.data(), m * 4, hipMemcpyHostToDevice, st));
+    MCF_TRY(hipMemsetAsync(b + p.part, 0, (size_t)s->pl.total * 8, st));
+    std::memset(s->hs, 0, sizeof(DevScalars));
+    s->hs->eta = eta;
+    s->hs->stop_enabled = 1;
+    MCF_TRY(hipMemcpyAsync(b + p.sc, s->hs, sizeof(DevScalars), hipMemcpyHostToDevice, st));
+    MCF_TRY(hipStreamSynchronize(st));  // the host vectors above go out of scope
+    return MCF_OK;
+}
+
+template <typename T>
+int do_reset(mcf_solver *s)
+{
+    MCF_TRY(launch_init<T>(s->c, s->bufs<T>(), s->opt.omega0, s->stream));
+    MCF_TRY(hipMemcpyAsync(s->hs, s->dsc(), sizeof(DevScalars), hipMemcpyDeviceToHost, s->stream));
+    MCF_TRY(hipStreamSynchronize(s->stream));
+    s->state = MCF_RUNNING;
+    return MCF_OK;
+}
+
+int reset_any(mcf_solver *s) { return s->precision == MCF_FP32 ? do_reset<float>(s) : do_reset<double>(s); }
+
+// Writes the host mirror's control fields to the device (stream idle).
+int push_scalars(mcf_solver *s)
+{
+    MCF_TRY(hipMemcpyAsync(s->dsc(), s->hs, sizeof(DevScalars), hipMemcpyHostToDevice, s->stream));
+    return MCF_OK;
+}
+
+int pull_scalars(mcf_solver *s)
+{
+    MCF_TRY(hipMemcpyAsync(s->hs, s->dsc(), sizeof(DevScalars), hipMemcpyDeviceToHost, s->stream));
+    MCF_TRY(hipStreamSynchronize(s->stream));
+    return MCF_OK;
+}
+
+hipEvent_t next_event(mcf_solver *s)
+{
+    if (s->ev_used == s->ev.size()) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        s->ev.push_back(e);
+    }
+    return s->ev[s->ev_used++];
+}
+
+int collect_events(mcf_solver *s)
+{
+    for (size_t k = 0; k + 1 < s->ev_used; k += 2) {
+        float ms = 0.f;
+        MCF_TRY(hipEventElapsedTime(&ms, s->ev[k], s->ev[k + 1]));
+        s->edge_ms += ms;
+        s->edge_launches += 1;
+    }
+    s->ev_used = 0;
+    return MCF_OK;
+}
+
+// Enqueues `count` iterations; only the last one is a check iteration.
+template <typename T>
+int enqueue_block(mcf_solver *s, long long count)
+{
+    const Bufs<T> b = s->bufs<T>();
+    for (long long it = 0; it < count; ++it) {
+        const bool check = it == count - 1;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (s->timing) {
+            e0 = next_event(s);
+            e1 = next_event(s);
+            if (!e0 || !e1) return MCF_E_DEVICE;
+            MCF_TRY(hipEventRecord(e0, s->stream));
+        }
+        MCF_TRY(launch_edge<T>(s->c, b, s->pl, s->sh, check, s->stream));
+        if (s->timing) MCF_TRY(hipEventRecord(e1, s->stream));
+        MCF_TRY(launch_node<T>(s->c, b, s->pl, check, s->stream));
+        if (check) MCF_TRY(launch_residual<T>(s->c, b, s->pl, s->sh, s->stream));
+        MCF_TRY(launch_control<T>(s->c, b, s->pl, check, s->stream));
+    }
+    return MCF_OK;
+}
+
+// The iteration driver.  With stop_test the device raises `stop` when the stop rule
+// holds at a check; the host polls the scalars after every block of check_every
+// iterations.  Without it, exactly target - k iterations run (divergence still stops).
+int drive(mcf_solver *s, long long target, bool stop_test)
+{
+    auto t0 = std::chrono::steady_clock::now();
+    int rc = pull_scalars(s);
+    if (rc) return rc;
+    if (!stop_test || s->hs->state == MCF_RUNNING) {
+        s->hs->stop = s->hs->state == MCF_DIVERGED ? 1 : 0;
+        s->hs->stop_enabled = stop_test ? 1 : 0;
+        if ((rc = push_scalars(s))) return rc;
+    }
+    const long long K = std::max(1, s->opt.check_every);
+    for (;;) {
+        if (s->hs->stop) {
+            s->state = s->hs->state == MCF_DIVERGED ? MCF_DIVERGED : MCF_CONVERGED;
+            break;
+        }
+        if (s->hs->k >= target) {
+            s->state = stop_test ? MCF_MAX_ITER : MCF_RUNNING;
+            break;
+        }
+        const long long count = std::min(K, target - s->hs->k);
+        rc = s->precision == MCF_FP32 ? enqueue_block<float>(s, count) : enqueue_block<double>(s, count);
+        if (rc) return rc;
+        if ((rc = pull_scalars(s))) return rc;
+        if (s->timing && (rc = collect_events(s))) return rc;
+    }
+    s->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return MCF_OK;
+}
+
+template <typename T>
+int download_cols(mcf_solver *s, size_t off, int cols, bool edge_order, double *out)
+{
+    const int n = s->n;
+    const long long ld = s->ld;
+    std::vector<T> tmp((size_t)ld * cols);
+    MCF_TRY(hipMemcpyAsync(tmp.data(), s->base + off, tmp.size() * sizeof(T), hipMemcpyDeviceToHost, s->stream));
+    MCF_TRY(hipStreamSynchronize(s->stream));
+    for (int c = 0; c < cols; ++c) {
+        const int dst = edge_order ? s->perm[c] : c;
+        for (int i = 0; i < n; ++i) out[(size_t)dst * n + i] = (double)tmp[(size_t)c * ld + i];
+    }
+    return MCF_OK;
+}
+
+template <typename T>
+int upload_cols(mcf_solver *s, size_t off, int cols, bool edge_order, const double *in)
+{
+    const int n = s->n;
+    const long long ld = s->ld;
+    std::vector<T> tmp((size_t)ld * cols, T(0));
+    for (int c = 0; c < cols; ++c) {
+        const int src = edge_order ? s->perm[c] : c;
+        for (int i = 0; i < n; ++i) tmp[(size_t)c * ld + i] = (T)in[(size_t)src * n + i];
+    }
+    MCF_TRY(hipMemcpyAsync(s->base + off, tmp.data(), tmp.size() * sizeof(T), hipMemcpyHostToDevice, s->stream));
+    MCF_TRY(hipStreamSynchronize(s->stream));
+    return MCF_OK;
+}
+
+int download_any(mcf_solver *s, size_t off, int cols, bool edge_order, double *out)
+{
+    return s->precision == MCF_FP32 ? download_cols<float>(s, off, cols, edge_order, out)
+                                    : download_cols<double>(s, off, cols, edge_order, out);
+}
+
+int upload_any(mcf_solver *s, size_t off, int cols, bool edge_order, const double *in)
+{
+    return s->precision == MCF_FP32 ? upload_cols<float>(s, off, cols, edge_order, in)
+                                    : upload_cols<double>(s, off, cols, edge_order, in);
+}
+
+}  // namespace
+
+// ====================================================================== C ABI
+extern "C" {
+
+void mcf_options_default(mcf_options *o)
+{
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->tol = 1e-4;
+    o->max_iter = 100000;
+    o->precision = MCF_FP64;
+    o->stop_rule = MCF_STOP_REL_KKT;
+    o->check_every = 1;
+    o->k_adapt = 100;
+    o->rho = 1.9;
+    o->theta = 0.5;
+    o->tau = 1e-5;
+    o->omega0 = 1.0;
+    o->device = 0;
+}
+
+size_t mcf_workspace_bytes(int32_t n, int32_t m, int32_t precision)
+{
+    if (n < 2 || n > MAX_N || m < 1 || (precision != MCF_FP32 && precision != MCF_FP64)) return 0;
+    return make_plan(n, m, precision).total;
+}
+
+const char *mcf_strerror(int code)
+{
+    switch (code) {
+    case MCF_OK: return "ok";
+    case MCF_E_ARG: return "invalid argument";
+    case MCF_E_GRAPH: return "graph is not strongly connected";
+    case MCF_E_NOMEM: return "out of device memory";
+    case MCF_E_DEVICE: return "HIP device error";
+    case MCF_E_STATE: return "invalid solver state";
+    default: return "unknown error";
+    }
+}
+
+void mcf_destroy(mcf_solver *s)
+{
+    if (!s) return;
+    if (s->stream) (void)hipStreamSynchronize(s->stream);
+    for (hipEvent_t e : s->ev) (void)hipEventDestroy(e);
+    if (s->own_mem && s->base) (void)hipFree(s->base);
+    if (s->hs) (void)hipHostFree(s->hs);
+    if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
+    delete s;
+}
+
+int mcf_create(int32_t n, int32_t m, const int32_t *tail, const int32_t *head, const double *cap, int32_t utility,
+               double gamma, const double *w, const mcf_options *opt, mcf_solver **out)
+{
+    if (!out) return MCF_E_ARG;
+    *out = nullptr;
+    mcf_options o;
+    if (opt) o = *opt;
+    else mcf_options_default(&o);
+    if (n < 2 || n > MAX_N || m < 1 || !tail || !head || !cap || !w) return MCF_E_ARG;
+    if (utility != MCF_UTIL_LOG && utility != MCF_UTIL_POWER) return MCF_E_ARG;
+    if (utility == MCF_UTIL_POWER && !(gamma > 0.0 && gamma < 1.0)) return MCF_E_ARG;
+    if (!(o.tol > 0.0) || (o.precision != MCF_FP32 && o.precision != MCF_FP64)) return MCF_E_ARG;
+    if (o.stop_rule != MCF_STOP_REL_KKT && o.stop_rule != MCF_STOP_PAPER) return MCF_E_ARG;
+    if (!(o.rho > 0.0 && o.rho < 2.0) || !(o.omega0 > 0.0) || !(o.theta >= 0.0 && o.theta <= 1.0)) return MCF_E_ARG;
+    if (o.check_every < 1) o.check_every = 1;
+    for (int l = 0; l < m; ++l) {
+        if (tail[l] < 0 || tail[l] >= n || head[l] < 0 || head[l] >= n || tail[l] == head[l]) return MCF_E_ARG;
+        if (!(cap[l] > 0.0) || !std::isfinite(cap[l])) return MCF_E_ARG;
+    }
+    for (int j = 0; j < n; ++j)
+        for (int i = 0; i < n; ++i)
+            if (i != j) {
+                const double x = w[(size_t)j * n + i];
+                if (!(x > 0.0) || !std::isfinite(x)) return MCF_E_ARG;
+            }
+    if (!strongly_connected(n, m, tail, head)) return MCF_E_GRAPH;
+
+    mcf_solver *s = new (std::nothrow) mcf_solver();
+    if (!s) return MCF_E_NOMEM;
+    s->n = n;
+    s->m = m;
+    s->precision = o.precision;
+    s->opt = o;
+    s->ld = padded_ld(n);
+    s->sh = edge_shape_for(n);
+    s->plan = make_plan(n, m, o.precision);
+    s->pl = part_layout(m, node_blocks(n));
+    Consts &c = s->c;
+    c.n = n;
+    c.m = m;
+    c.ld = s->ld;
+    c.utility = utility;
+    c.gamma = utility == MCF_UTIL_POWER ? gamma : 0.0;
+    c.c1 = utility == MCF_UTIL_POWER ? gamma / (1.0 - gamma) : 0.0;
+    c.rho = o.rho;
+    c.theta = o.theta;
+    c.tau = o.tau;
+    c.tol = o.tol;
+    c.k_adapt = o.k_adapt;
+    c.stop_rule = o.stop_rule;
+    c.nblk_node = node_blocks(n);
+
+    int rc = MCF_OK;
+    if (hipSetDevice(o.device) != hipSuccess) rc = MCF_E_DEVICE;
+    if (!rc) {
+        if (o.stream) {
+            s->stream = (hipStream_t)o.stream;
+        } else if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) == hipSuccess) {
+            s->own_stream = true;
+        } else {
+            rc = MCF_E_DEVICE;
+        }
+    }
+    if (!rc && hipHostMalloc((void **)&s->hs, sizeof(DevScalars), hipHostMallocDefault) != hipSuccess)
+        rc = MCF_E_NOMEM;
+    if (!rc) {
+        if (o.workspace) {
+            if (o.workspace_bytes < s->plan.total || ((uintptr_t)o.workspace % ALIGN)) rc = MCF_E_ARG;
+            else s->base = (char *)o.workspace;
+        } else {
+            hipError_t e = hipMalloc((void **)&s->base, s->plan.total);
+            if (e != hipSuccess) rc = hip_err(e);
+            else s->own_mem = true;
+        }
+    }
+    if (!rc) {
+        rc = o.precision == MCF_FP32 ? upload_problem<float>(s, tail, head, cap, w)
+                                     : upload_problem<double>(s, tail, head, cap, w);
+    }
+    if (!rc) rc = reset_any(s);
+    if (rc) {
+        mcf_destroy(s);
+        return rc;
+    }
+    *out = s;
+    return MCF_OK;
+}
+
+int mcf_reset(mcf_solver *s)
+{
+    if (!s) return MCF_E_ARG;
+    return reset_any(s);
+}
+
+int mcf_solve(mcf_solver *s)
+{
+    if (!s) return MCF_E_ARG;
+    return drive(s, s->opt.max_iter, true);
+}
+
+int mcf_run(mcf_solver *s, int64_t iters)
+{
+    if (!s || iters < 0) return MCF_E_ARG;
+    int rc = pull_scalars(s);
+    if (rc) return rc;
+    if (s->hs->state == MCF_CONVERGED) {  // run on past a met stop rule
+        s->hs->state = MCF_RUNNING;
+        s->hs->stop = 0;
+        if ((rc = push_scalars(s))) return rc;
+    }
+    return drive(s, s->hs->k + iters, false);
+}
+
+int mcf_status(const mcf_solver *s, mcf_result *r)
+{
+    if (!s || !r) return MCF_E_ARG;
+    const DevScalars &h = *s->hs;
+    std::memset(r, 0, sizeof(*r));
+    r->state = s->state;
+    r->checked = h.checked;
+    r->iters = h.k;
+    r->r = h.r;
+    r->r_paper = h.r_paper;
+    r->rel_primal = h.rel_primal;
+    r->rel_dual = h.rel_dual;
+    r->rel_gap = h.rel_gap;
+    r->rel_kkt = h.rel_kkt;
+    r->primal_obj = h.primal_obj;
+    r->dual_obj = h.dual_obj;
+    r->infeasible_frac = h.infeasible_frac;
+    r->omega = h.omega;
+    r->alpha = h.alpha;
+    r->beta = h.beta;
+    r->delta_f = h.dF;
+    r->delta_y = h.dY;
+    r->seconds = s->seconds;
+    return MCF_OK;
+}
+
+int mcf_get_solution(mcf_solver *s, double *F, double *T, double *Y)
+{
+    if (!s) return MCF_E_ARG;
+    int rc = MCF_OK;
+    if (F && (rc = download_any(s, s->plan.Fhat, s->m, true, F))) return rc;
+    if (T && (rc = download_cols<double>(s, s->plan.That, s->n, false, T))) return rc;
+    if (Y && (rc = download_any(s, s->plan.Y, s->n, false, Y))) return rc;
+    return MCF_OK;
+}
+
+int mcf_get_state(mcf_solver *s, double *F, double *Y, mcf_scalars *sc)
+{
+    if (!s) return MCF_E_ARG;
+    int rc = MCF_OK;
+    if (F && (rc = download_any(s, s->plan.F, s->m, true, F))) return rc;
+    if (Y && (rc = download_any(s, s->plan.Y, s->n, false, Y))) return rc;
+    if (sc) {
+        if ((rc = pull_scalars(s))) return rc;
+        sc->k = s->hs->k;
+        sc->omega = s->hs->omega;
+    }
+    return MCF_OK;
+}
+
+int mcf_set_state(mcf_solver *s, const double *F, const double *Y, const mcf_scalars *sc)
+{
+    if (!s || !F) return MCF_E_ARG;
+    if (sc && (!(sc->omega > 0.0) || sc->k < 0)) return MCF_E_ARG;
+    int rc = upload_any(s, s->plan.F, s->m, true, F);
+    if (!rc && Y) rc = upload_any(s, s->plan.Y, s->n, false, Y);
+    if (rc) return rc;
+    if ((rc = pull_scalars(s))) return rc;
+    if (sc) {
+        s->hs->k = sc->k;
+        s->hs->omega = sc->omega;
+        s->hs->alpha = s->hs->eta / sc->omega;
+        s->hs->beta = s->hs->eta * sc->omega;
+    }
+    s->hs->stop = 0;
+    s->hs->state = MCF_RUNNING;
+    s->hs->checked = 0;
+    s->state = MCF_RUNNING;
+    if ((rc = push_scalars(s))) return rc;
+    MCF_TRY(hipStreamSynchronize(s->stream));
+    return MCF_OK;
+}
+
+int mcf_debug_poison(mcf_solver *s, int32_t which, int64_t index)
+{
+    if (!s || (which != 0 && which != 1)) return MCF_E_ARG;
+    const int n = s->n;
+    const long long cols = which == 0 ? s->m : n;
+    if (index < 0 || index >= cols * n) return MCF_E_ARG;
+    long long col = index / n, i = index % n;
+    if (which == 0) {
+        // user edge -> internal column
+        long long internal = -1;
+        for (int e = 0; e < s->m; ++e)
+            if (s->perm[e] == col) internal = e;
+        col = internal;
+    }
+    const long long off = col * s->ld + i;
+    hipError_t e = s->precision == MCF_FP32 ? launch_poison<float>(s->bufs<float>(), which, off, s->stream)
+                                            : launch_poison<double>(s->bufs<double>(), which, off, s->stream);
+    MCF_TRY(e);
+    MCF_TRY(hipStreamSynchronize(s->stream));
+    return MCF_OK;
+}
+
+int mcf_enable_kernel_timing(mcf_solver *s, int32_t enable)
+{
+    if (!s) return MCF_E_ARG;
+    s->timing = enable != 0;
+    s->ev_used = 0;
+    s->edge_ms = 0.0;
+    s->edge_launches = 0;
+    return MCF_OK;
+}
+
+int mcf_kernel_time(mcf_solver *s, double *edge_ms, int64_t *edge_launches)
+{
+    if (!s) return MCF_E_ARG;
+    if (edge_ms) *edge_ms = s->edge_ms;
+    if (edge_launches) *edge_launches = s->edge_launches;
+    return MCF_OK;
+}
+
+int mcf_layout(const mcf_solver *s, int32_t *ld, int32_t *edge_block, int32_t *edge_ept)
+{
+    if (!s) return MCF_E_ARG;
+    if (ld) *ld = (int32_t)s->ld;
+    if (edge_block) *edge_block = s->sh.block;
+    if (edge_ept) *edge_ept = s->sh.ept;
+    return MCF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,104 @@
+"""The C-ABI library loads and exports every symbol include/mcf.h declares, and
+its host-side validation answers without a GPU.  CPU only."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2501_17996_amd import instances as I
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "mcf.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(mcf_[a-z_]+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def mcf():
+    from paper_2501_17996_amd import build, mcf as M
+    if not os.path.exists(M.LIB_PATH):
+        build.build()
+    return M
+
+
+def test_every_declared_symbol_is_exported(mcf):
+    L = mcf.lib()
+    names = _declared()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(L, name), name
+    assert set(names) == set(mcf.EXPORTED)
+
+
+def test_options_defaults_are_the_papers(mcf):
+    import json
+    o = mcf.mcf_options_default()
+    g = json.load(open(os.path.join(ROOT, "tests", "golden", "paper_parameters.json")))
+    assert o.rho == g["rho"]["value"] and o.theta == g["theta"]["value"] and o.tau == g["tau"]["value"]
+    assert o.k_adapt == g["k_adapt"]["value"] and o.omega0 == g["omega0"]["value"]
+    assert o.tol == 1e-4 and o.precision == mcf.MCF_FP64 and o.check_every == 1
+
+
+def test_workspace_bytes(mcf):
+    a = mcf.mcf_workspace_bytes(200, 2000, mcf.MCF_FP32)
+    b = mcf.mcf_workspace_bytes(200, 2000, mcf.MCF_FP64)
+    assert 0 < a < b
+    # four n x m iterate arrays dominate: 4 * 256 * 2000 * 4 bytes in FP32 (ld = n padded to 64)
+    assert a >= 4 * 256 * 2000 * 4
+    assert mcf.mcf_workspace_bytes(1, 10, 0) == 0
+    assert mcf.mcf_workspace_bytes(10, 0, 0) == 0
+    assert mcf.mcf_workspace_bytes(16385, 10, 0) == 0
+
+
+def test_strerror(mcf):
+    assert mcf.mcf_strerror(0) == "ok"
+    assert "strongly" in mcf.mcf_strerror(mcf.MCF_E_GRAPH)
+    assert mcf.mcf_strerror(-99) == "unknown error"
+
+
+def _expect(mcf, code, **kw):
+    inst = I.config1(0)
+    args = dict(n=inst.n, tail=inst.tail, head=inst.head, cap=inst.cap, utility=inst.utility, gamma=inst.gamma,
+                w=inst.w)
+    args.update(kw)
+    with pytest.raises(mcf.MCFError) as ei:
+        mcf.mcf_create(args["n"], args["tail"], args["head"], args["cap"], args["utility"], args["gamma"],
+                       args["w"], kw.get("opt"))
+    assert ei.value.code == code
+
+
+def test_validation_errors(mcf):
+    inst = I.config1(0)
+    E = mcf.MCF_E_ARG
+    t = inst.tail.copy(); t[3] = 10
+    _expect(mcf, E, tail=t)                                   # index out of range
+    t = inst.tail.copy(); t[0] = inst.head[0]
+    _expect(mcf, E, tail=t)                                   # self-loop
+    c = inst.cap.copy(); c[5] = 0.0
+    _expect(mcf, E, cap=c)                                    # c <= 0
+    c = inst.cap.copy(); c[5] = np.inf
+    _expect(mcf, E, cap=c)
+    w = inst.w.copy(); w[1] = np.nan
+    _expect(mcf, E, w=w)                                      # NaN weight off the diagonal
+    w = inst.w.copy(); w[0] = np.nan                          # the diagonal is ignored ...
+    _expect(mcf, E, w=w, utility=1, gamma=1.0)                # ... but gamma must be in (0, 1)
+    _expect(mcf, E, utility=7)
+    _expect(mcf, E, n=1)
+    o = mcf.mcf_options_default(); o.tol = 0.0
+    _expect(mcf, E, opt=o)
+    o = mcf.mcf_options_default(); o.rho = 2.0
+    _expect(mcf, E, opt=o)
+
+
+def test_graph_not_strongly_connected(mcf):
+    # a directed path 0 -> 1 -> 2 plus 2 -> 1: node 0 is never reached back
+    tail = np.array([0, 1, 2], np.int32)
+    head = np.array([1, 2, 1], np.int32)
+    w = np.ones(9)
+    with pytest.raises(mcf.MCFError) as ei:
+        mcf.mcf_create(3, tail, head, np.ones(3), 0, 0.0, w)
+    assert ei.value.code == mcf.MCF_E_GRAPH

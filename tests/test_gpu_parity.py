@@ -1,0 +1,329 @@
+"""Parity of the HIP solver (through the C-ABI) with the FP64 CPU oracle.
+
+FP64 iterates must match the oracle iteration by iteration to 1e-10 relative
+(normwise, max-abs); FP32 iterates are held to FP32-rounding tolerances and to
+the objective of the FP64 oracle within 1e-5 relative at the same KKT
+tolerance.  Every input is a seeded synthetic instance from
+paper_2501_17996_amd.instances."""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2501_17996_amd import instances as I
+
+pytestmark = pytest.mark.gpu
+
+THREADS = max(1, min(16, os.cpu_count() or 1))
+RTOL64 = 1e-10
+
+
+@pytest.fixture(scope="module")
+def M():
+    from paper_2501_17996_amd import mcf
+    mcf.lib()
+    return mcf
+
+
+@pytest.fixture(autouse=True)
+def _announce(request):
+    print(f"\n[gpu-case] {request.node.nodeid}", flush=True)
+    sys.stdout.flush()
+    yield
+
+
+def relerr(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    scale = max(float(np.max(np.abs(b))), 1e-300)
+    return float(np.max(np.abs(a - b))) / scale
+
+
+def gpu_solver(M, inst, precision=0, **kw):
+    return M.Solver(inst, precision=precision, **kw)
+
+
+def assert_state_close(S, O, rtol=RTOL64, what=""):
+    Fg, Yg, sg = S.get_state()
+    Fo, Yo, so = O.get_state()
+    assert sg["k"] == so["k"], what
+    ef, ey = relerr(Fg, Fo), relerr(Yg, Yo)
+    assert ef <= rtol and ey <= rtol, f"{what} k={sg['k']} F err {ef:.3e} Y err {ey:.3e}"
+    assert sg["omega"] == pytest.approx(so["omega"], rel=rtol), what
+    return ef, ey
+
+
+def assert_metrics_close(g, o, rtol=1e-8, what=""):
+    """Check-iteration quantities.  r and rel_* sit on cancellations (a - b^2/e), so
+    they get a looser tolerance; finiteness must agree except at a feasibility flip."""
+    for key in ("rel_kkt", "rel_dual", "rel_primal", "rel_gap", "primal_obj", "dual_obj"):
+        a, b = g[key], o[key]
+        if math.isfinite(b) and math.isfinite(a):
+            assert a == pytest.approx(b, rel=rtol, abs=1e-9), f"{what} {key}: {a} vs {b}"
+    assert abs(g["infeasible_frac"] - o["infeasible_frac"]) <= 3.0 / 90 + 1e-12, what
+
+
+# ------------------------------------------------------------ trajectory FP64
+@pytest.mark.parametrize("seed", range(5))
+def test_c1_trajectory_fp64_every_iteration(M, seed):
+    inst = I.config1(seed)
+    S = gpu_solver(M, inst, tol=1e-6)
+    O = oracle.OracleSolver(inst)
+    worst = 0.0
+    for k in range(1, 701):
+        S.run(1)
+        mo = O.step(check=True)
+        ef, ey = assert_state_close(S, O, what=f"c1 seed {seed}")
+        worst = max(worst, ef, ey)
+        assert_metrics_close(S.status(), mo, what=f"c1 seed {seed} k {k}")
+    print(f"c1 seed {seed}: worst relative error over 700 iterations {worst:.2e}")
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_c1_solve_iterations_match_oracle(M, seed):
+    inst = I.config1(seed)
+    S = gpu_solver(M, inst, tol=1e-6)
+    st = S.solve()
+    O = oracle.OracleSolver(inst)
+    assert O.solve(1e-6) == "converged"
+    mo = O.metrics()
+    assert st["state_name"] == "converged"
+    assert st["iters"] == int(mo["k"])
+    assert st["rel_kkt"] <= 1e-6
+    F, T, Y = S.solution()
+    Fo, To, _ = O.get_last()
+    assert relerr(T, To) < 1e-9 and relerr(F, Fo) < 1e-9
+
+
+def test_c2_fp64_checkpoints_and_solve(M):
+    inst = I.config2(0)
+    S = gpu_solver(M, inst, tol=1e-4)
+    O = oracle.OracleSolver(inst, threads=THREADS)
+    done = 0
+    for k in [1, 2, 3, 4, 5, 10, 20, 50, 100, 101, 200, 400, 800, 1500]:
+        S.run(k - done)
+        O.run(k - done, check=False)
+        done = k
+        ef, ey = assert_state_close(S, O, what="c2 fp64")
+        print(f"c2 fp64 k={k}: F err {ef:.2e} Y err {ey:.2e}", flush=True)
+    # a full solve from the cold start: same stopping iteration, same solution
+    S2 = gpu_solver(M, inst, tol=1e-4)
+    st = S2.solve()
+    O2 = oracle.OracleSolver(inst, threads=THREADS)
+    assert O2.solve(1e-4) == "converged"
+    mo = O2.metrics()
+    print(f"c2 fp64 solve: gpu {st['iters']} iters, oracle {int(mo['k'])}", flush=True)
+    assert abs(st["iters"] - int(mo["k"])) <= 1
+    F, T, Y = S2.solution()
+    _, To, _ = O2.get_last()
+    assert relerr(T, To) < 1e-8
+    assert st["primal_obj"] == pytest.approx(mo["primal_obj"], rel=1e-10)
+
+
+# ------------------------------------------------------------ FP32 accuracy
+@pytest.mark.parametrize("seed", [0, 1])
+def test_c2_fp32_objective_matches_fp64_oracle(M, seed):
+    inst = I.config2(seed)
+    S = gpu_solver(M, inst, precision=1, tol=1e-4)
+    st = S.solve()
+    assert st["state_name"] == "converged", st
+    O = oracle.OracleSolver(inst, threads=THREADS)
+    assert O.solve(1e-4) == "converged"
+    u64 = -O.metrics()["primal_obj"]
+    u32 = -st["primal_obj"]
+    rel = abs(u32 - u64) / max(1.0, abs(u64))
+    print(f"c2 fp32 seed {seed}: U32 {u32:.10g} U64 {u64:.10g} rel {rel:.2e} iters {st['iters']} "
+          f"vs {int(O.metrics()['k'])}", flush=True)
+    assert rel <= 1e-5
+
+
+def test_c2_fp32_trajectory_tracks_oracle(M):
+    """Early FP32 iterates stay within FP32 rounding of the FP64 oracle."""
+    inst = I.config2(0)
+    S = gpu_solver(M, inst, precision=1)
+    O = oracle.OracleSolver(inst, threads=THREADS)
+    for k in (1, 2, 5, 10):
+        S.run(1 if k == 1 else k - prev)
+        O.run(1 if k == 1 else k - prev, check=False)
+        prev = k
+        Fg, Yg, _ = S.get_state()
+        Fo, Yo, _ = O.get_state()
+        assert relerr(Fg, Fo) < 1e-5 * k and relerr(Yg, Yo) < 1e-5 * k, k
+
+
+# ------------------------------------------------ power utility, larger shapes
+@pytest.mark.parametrize("gamma", [0.5, 0.3])
+def test_power_utility_trajectory(M, gamma):
+    inst = I.ring_instance(150, 6, seed=3, utility=I.UTIL_POWER, gamma=gamma)
+    S = gpu_solver(M, inst)
+    O = oracle.OracleSolver(inst, threads=THREADS)
+    for k in range(1, 41):
+        S.run(1)
+        mo = O.step(check=True)
+        assert_state_close(S, O, what=f"power {gamma}")
+        assert_metrics_close(S.status(), mo, what=f"power {gamma} k {k}")
+    S.run(300)
+    O.run(300, check=False)
+    assert_state_close(S, O, rtol=1e-9, what=f"power {gamma} k 340")
+
+
+def test_c3_fp64_first_iterations(M):
+    inst = I.config3(0)
+    S = gpu_solver(M, inst)
+    O = oracle.OracleSolver(inst, threads=THREADS)
+    for k in range(1, 4):
+        S.run(1)
+        mo = O.step(check=True)
+        assert_state_close(S, O, what="c3 fp64")
+        assert_metrics_close(S.status(), mo, what=f"c3 k {k}")
+
+
+# ----------------------------------------------- edge shapes and ragged tails
+def _sampled_step_check(M, inst, precision, iters_before=3, n_edges=12, n_nodes=4, seed=0):
+    """Full-size check on sampled outputs: from the GPU state after a few iterations,
+    one more GPU iteration; the oracle recomputes sampled edge columns of F and
+    sampled node columns of Y from the same state."""
+    S = gpu_solver(M, inst, precision=precision)
+    S.run(iters_before)
+    F0, Y0, sc0 = S.get_state()
+    S.run(1)
+    F1, Y1, sc1 = S.get_state()
+    n, m = inst.n, inst.m
+    eta = oracle.eta(n, inst.tail, inst.head)
+    alpha, beta = eta / sc0["omega"], eta * sc0["omega"]
+    rng = np.random.default_rng(seed)
+    F0m, F1m = F0.reshape(m, n), F1.reshape(m, n)
+    Y0m, Y1m = Y0.reshape(n, n), Y1.reshape(n, n)
+    W = np.asarray(inst.w).reshape(n, n)
+    if precision == 1:  # the device holds the weights in FP32
+        W = W.astype(np.float32).astype(np.float64)
+    tol = RTOL64 if precision == 0 else 2e-5
+    for l in rng.choice(m, size=min(n_edges, m), replace=False):
+        _, _, fnew, _ = oracle.edge_column(F0m[l], Y0m[inst.head[l]], Y0m[inst.tail[l]], alpha, inst.cap[l], 1.9)
+        scale = max(np.max(np.abs(fnew)), np.max(np.abs(F0m[l])), 1e-30)
+        assert np.max(np.abs(F1m[l] - fnew)) <= tol * scale, ("edge", int(l))
+    for j in rng.choice(n, size=min(n_nodes, n), replace=False):
+        ins = np.nonzero(inst.head == j)[0]
+        outs = np.nonzero(inst.tail == j)[0]
+        fb = {}
+        for l in np.concatenate([ins, outs]):
+            _, fbar, _, _ = oracle.edge_column(F0m[l], Y0m[inst.head[l]], Y0m[inst.tail[l]], alpha,
+                                               inst.cap[l], 1.9)
+            fb[int(l)] = fbar
+        fin = np.stack([fb[int(l)] for l in ins])
+        fout = np.stack([fb[int(l)] for l in outs])
+        _, _, ynew = oracle.node_column(j, fin, fout, Y0m[j], W[j], beta, 1.9, inst.utility, inst.gamma)
+        scale = np.max(np.abs(Y0m[j])) + beta * np.max(np.sum(np.abs(fin), 0) + np.sum(np.abs(fout), 0)) + 1.0
+        err = np.max(np.abs(Y1m[j] - ynew))
+        assert err <= tol * scale, ("node", int(j), err, scale)
+
+
+@pytest.mark.parametrize("n", [3, 63, 64, 65, 127, 129, 257, 300, 513, 1025, 2049, 4097])
+def test_shapes_fp64_against_oracle(M, n):
+    inst = I.ring_instance(n, 3, seed=n)
+    if n <= 1025:
+        S = gpu_solver(M, inst)
+        O = oracle.OracleSolver(inst, threads=THREADS)
+        for _ in range(3):
+            S.run(1)
+            mo = O.step(check=True)
+            assert_state_close(S, O, what=f"shape n={n}")
+            assert_metrics_close(S.status(), mo, what=f"shape n={n}")
+    else:
+        _sampled_step_check(M, inst, 0)
+
+
+@pytest.mark.parametrize("n,precision", [(8193, 1), (12000, 0), (16384, 1)])
+def test_large_shapes_sampled(M, n, precision):
+    inst = I.ring_instance(n, 2, seed=n)
+    _sampled_step_check(M, inst, precision, iters_before=2, n_edges=8, n_nodes=3)
+
+
+def test_c4_full_size_sampled(M):
+    """n = 1e4, m = 1e5, FP32 iterates: sampled outputs of one iteration."""
+    inst = I.config4(0)
+    _sampled_step_check(M, inst, 1, iters_before=3, n_edges=10, n_nodes=3)
+
+
+def test_c3_fp32_sampled(M):
+    inst = I.config3(0)
+    _sampled_step_check(M, inst, 1, iters_before=20, n_edges=20, n_nodes=6)
+
+
+# ------------------------------------------------------- closed forms on GPU
+def test_cf1_two_nodes_gpu(M):
+    c = np.array([0.7, 1.3])
+    w = np.array([0.0, 1.2, 0.9, 0.0])  # w[j*n+i]
+    inst = I.Instance(2, np.array([1, 0], np.int32), np.array([0, 1], np.int32), c, 0, 0.0, w)
+    for precision in (0, 1):
+        S = gpu_solver(M, inst, precision=precision, tol=1e-7 if precision == 0 else 1e-5)
+        st = S.solve()
+        assert st["state_name"] == "converged"
+        _, T, _ = S.solution()
+        Tm = T.reshape(2, 2).T
+        tol = 1e-6 if precision == 0 else 1e-4
+        assert Tm[0, 1] == pytest.approx(c[0], rel=tol) and Tm[1, 0] == pytest.approx(c[1], rel=tol)
+
+
+# ------------------------------------------------------------- host control
+def test_determinism_bitwise(M):
+    inst = I.config2(2)
+    outs = []
+    for _ in range(2):
+        S = gpu_solver(M, inst, precision=1)
+        S.run(250)
+        outs.append(S.get_state())
+    np.testing.assert_array_equal(outs[0][0], outs[1][0])
+    np.testing.assert_array_equal(outs[0][1], outs[1][1])
+
+
+def test_resume_equals_uninterrupted(M):
+    inst = I.config2(3)
+    A = gpu_solver(M, inst)
+    A.run(300)
+    B = gpu_solver(M, inst)
+    B.run(120)
+    F, Y, sc = B.get_state()
+    C = gpu_solver(M, inst)
+    C.set_state(F, Y, k=sc["k"], omega=sc["omega"])
+    C.run(180)
+    Fa, Ya, sa = A.get_state()
+    Fc, Yc, scc = C.get_state()
+    assert sa == scc
+    np.testing.assert_array_equal(Fa, Fc)
+    np.testing.assert_array_equal(Ya, Yc)
+
+
+def test_states_max_iter_divergence_reset(M):
+    inst = I.config1(0)
+    S = gpu_solver(M, inst, tol=1e-6, max_iter=7)
+    st = S.solve()
+    assert st["state_name"] == "max_iter" and st["iters"] == 7
+    S.run(3)
+    S.poison("F", 5)
+    S.run(2)
+    st = S.status()
+    assert st["state_name"] == "diverged"
+    S.reset()
+    st = S.solve()
+    assert st["iters"] == 7 and st["state_name"] == "max_iter"
+
+
+def test_paper_stop_rule_matches_oracle(M):
+    inst = I.config1(3)
+    eps = 0.01 / (inst.n * (inst.n - 1))
+    S = gpu_solver(M, inst, tol=eps, stop_rule=1)
+    st = S.solve()
+    O = oracle.OracleSolver(inst)
+    assert O.solve(eps, stop_rule=1) == "converged"
+    assert st["state_name"] == "converged" and st["iters"] == int(O.metrics()["k"])
+    assert st["r"] < inst.n * inst.m * eps
+
+
+def test_check_every_only_moves_the_stop(M):
+    inst = I.config1(1)
+    a = gpu_solver(M, inst, tol=1e-6, check_every=1).solve()
+    b = gpu_solver(M, inst, tol=1e-6, check_every=10).solve()
+    assert b["iters"] >= a["iters"] and b["iters"] - a["iters"] < 10 and b["iters"] % 10 == 0
