@@ -14,7 +14,7 @@ struct DevScalars {
     double dF, dY;
     double r, r_paper, rel_primal, rel_dual, rel_gap, rel_kkt;
     double primal_obj, dual_obj, infeasible_frac, a, b, e;
-    long long k;
+    long long k;  // iterations completed as of the last control launch (the host keeps the live count)
     int stop;     // 1: every kernel returns at entry (set on convergence or divergence)
     int state;    // MCF_RUNNING / MCF_CONVERGED / MCF_DIVERGED
     int checked;  // the check fields belong to the last iteration
@@ -29,6 +29,7 @@ struct Consts {
     double gamma, c1, rho, theta, tau, tol;
     int k_adapt, stop_rule;
     int nblk_node;         // node-phase blocks (partials per quantity)
+    int node_block;        // threads per node-phase block (64 or 256)
 };
 
 // Offsets (in doubles) of the partial-sum segments.
@@ -44,32 +45,38 @@ struct Bufs {
     double *That, *Up;
     const int *tail, *head, *out_off, *in_off, *in_edge;
     const double *cap;
+    double *mu;            // per-edge multiplier of the last projection (warm start of the next one)
     double *part;
     DevScalars *sc;
 };
 
-// Per-edge launch shape: BLOCK threads per edge column, EPT entries per thread.
+// Per-edge launch shape: `wpe` waves (of 64 lanes) per edge column, `ept` entries per lane.
+// With wpe == 1 a 256-thread block carries 4 edges, one per wave.
 struct EdgeShape {
-    int block, ept;
+    int wpe, ept;
 };
 EdgeShape edge_shape_for(int n);
 
 // Kernel launchers (defined in mcf_kernels.hip).
 template <typename T>
 hipError_t launch_init(const Consts &c, const Bufs<T> &b, double omega0, hipStream_t st);
+// `partial`: also write the ||dF||^2 / ||dY||^2 partials (iterations that end in a control launch).
 template <typename T>
 hipError_t launch_edge(const Consts &c, const Bufs<T> &b, const PartLayout &pl, EdgeShape sh, bool check,
-                       hipStream_t st);
+                       bool partial, hipStream_t st);
 template <typename T>
-hipError_t launch_node(const Consts &c, const Bufs<T> &b, const PartLayout &pl, bool check, hipStream_t st);
+hipError_t launch_node(const Consts &c, const Bufs<T> &b, const PartLayout &pl, bool check, bool partial,
+                       hipStream_t st);
 template <typename T>
 hipError_t launch_residual(const Consts &c, const Bufs<T> &b, const PartLayout &pl, EdgeShape sh,
                            hipStream_t st);
+// `adapt`: apply (e-primal_weight) if the step norms exceed tau; `k_after`: iterations done after this one.
 template <typename T>
-hipError_t launch_control(const Consts &c, const Bufs<T> &b, const PartLayout &pl, bool check, hipStream_t st);
+hipError_t launch_control(const Consts &c, const Bufs<T> &b, const PartLayout &pl, bool check, bool adapt,
+                          long long k_after, hipStream_t st);
 template <typename T>
 hipError_t launch_poison(const Bufs<T> &b, int which, long long offset, hipStream_t st);
 
-constexpr int NODE_BLOCK = 256;
+int node_block_for(int n);
 
 }  // namespace mcf

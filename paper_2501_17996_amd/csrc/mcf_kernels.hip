@@ -1,18 +1,19 @@
 // libmcf device kernels for gfx950 (CDNA4, wave64).
 //
-// One PDHG iteration of Algorithm 2.1 (eq. (e-pdhg-step)) is three launches:
-//   edge phase  : per edge column l (destination-major, contiguous n-vector):
-//                 q = F[:,l] + alpha (Y[:,head] - Y[:,tail]); Fhat = (q - mu)_+ (the
-//                 projection of Section 2.3, mu from an exact active-set search);
-//                 Fbar = 2 Fhat - F; F <- rho Fhat + (1 - rho) F; ||dF||^2 partial.
-//   node phase  : per node column j: V = Fbar A^T as a deterministic gather over the
-//                 in-edge and out-edge lists; Yhat = prox(Y - beta V) off the diagonal,
-//                 0 on it (Section 2.3); Y <- rho Yhat + (1 - rho) Y; ||dY||^2 partial.
-//   control     : FP64 fixed-order reduction of the partials, the adaptive primal
-//                 weight (e-primal_weight), the stop flag.
-// On check iterations the edge and node phases also produce Fhat, D = Fhat - Q,
-// T = -Fhat A^T and U' = u'(T), and a residual pass forms ||G||^2 and <G, D> for
-// r(Q) of (e-res).  No atomics anywhere: every sum has a fixed order.
+// One PDHG iteration of Algorithm 2.1 (eq. (e-pdhg-step)) is two launches:
+//   edge phase : per edge column l (destination-major, contiguous n-vector):
+//                q = F[:,l] + alpha (Y[:,head] - Y[:,tail]); Fhat = (q - mu)_+ (the
+//                projection of Section 2.3, mu from an exact active-set search);
+//                Fbar = 2 Fhat - F; F <- rho Fhat + (1 - rho) F.
+//   node phase : per node column j: V = Fbar A^T as a deterministic gather over the
+//                in-edge and out-edge lists; Yhat = prox(Y - beta V) off the diagonal,
+//                0 on it (Section 2.3); Y <- rho Yhat + (1 - rho) Y.
+// Iterations that adapt the primal weight (k a multiple of k_adapt) or check the
+// residual also write FP64 partials of ||dF||^2 and ||dY||^2 and end in a control
+// launch: FP64 fixed-order reduction, (e-primal_weight), the stop flag.  On check
+// iterations the edge and node phases also produce Fhat, D = Fhat - Q, T = -Fhat A^T
+// and U' = u'(T), and a residual pass forms ||G||^2 and <G, D> for r(Q) of (e-res).
+// No atomics anywhere: every sum has a fixed order, so results are deterministic.
 #include <math.h>
 
 #include "mcf_internal.h"
@@ -20,30 +21,76 @@
 namespace mcf {
 
 // ------------------------------------------------------------------ reductions
+// Wave-wide sums through DPP lane moves (quad xor 1, quad xor 2, row rotate 4 and 8)
+// leave every lane of a 16-lane row with the row total; the four row totals, read
+// from lanes 0/16/32/48, are added in row order.  The result is uniform (scalar) and
+// its rounding order is fixed.
+template <int CTRL>
+__device__ __forceinline__ int dpp_i32(int v)
+{
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = dpp_i32<CTRL>((int)(b & 0xffffffffLL));
+    const int hi = dpp_i32<CTRL>((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ __forceinline__ double lane_f64(double v, int lane)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+constexpr int DPP_QUAD_XOR1 = 0xB1;  // quad_perm [1,0,3,2]
+constexpr int DPP_QUAD_XOR2 = 0x4E;  // quad_perm [2,3,0,1]
+constexpr int DPP_ROW_ROR4 = 0x124;
+constexpr int DPP_ROW_ROR8 = 0x128;
+
 __device__ __forceinline__ double wave_sum(double v)
 {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
+    v += dpp_f64<DPP_QUAD_XOR1>(v);
+    v += dpp_f64<DPP_QUAD_XOR2>(v);
+    v += dpp_f64<DPP_ROW_ROR4>(v);
+    v += dpp_f64<DPP_ROW_ROR8>(v);
+    return ((lane_f64(v, 0) + lane_f64(v, 16)) + lane_f64(v, 32)) + lane_f64(v, 48);
+}
+
+__device__ __forceinline__ int wave_sum(int v)
+{
+    v += dpp_i32<DPP_QUAD_XOR1>(v);
+    v += dpp_i32<DPP_QUAD_XOR2>(v);
+    v += dpp_i32<DPP_ROW_ROR4>(v);
+    v += dpp_i32<DPP_ROW_ROR8>(v);
+    return __builtin_amdgcn_readlane(v, 0) + __builtin_amdgcn_readlane(v, 16) +
+           __builtin_amdgcn_readlane(v, 32) + __builtin_amdgcn_readlane(v, 48);
 }
 
 __device__ __forceinline__ double wave_max(double v)
 {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
-    return v;
+    v = fmax(v, dpp_f64<DPP_QUAD_XOR1>(v));
+    v = fmax(v, dpp_f64<DPP_QUAD_XOR2>(v));
+    v = fmax(v, dpp_f64<DPP_ROW_ROR4>(v));
+    v = fmax(v, dpp_f64<DPP_ROW_ROR8>(v));
+    return fmax(fmax(lane_f64(v, 0), lane_f64(v, 16)), fmax(lane_f64(v, 32), lane_f64(v, 48)));
 }
 
-// Block-wide sums of x and y, returned identically to every thread.  The wave
-// partials are combined in wave order, so the result is deterministic.
-template <int BLOCK>
-__device__ __forceinline__ void block_sum2(double &x, double &y, double *lds)
+// Sums over a group of NW waves (one edge column or one node block): wave sums,
+// then the NW wave totals added in wave order through LDS.  NW == 1 needs no LDS.
+// `lds` must hold 2*NW doubles and be private to the group.
+template <int NW>
+__device__ __forceinline__ void group_sum(double &x, double &y, double *lds)
 {
     x = wave_sum(x);
     y = wave_sum(y);
-    if constexpr (BLOCK > 64) {
-        constexpr int NW = BLOCK / 64;
-        const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if constexpr (NW > 1) {
+        const int lane = threadIdx.x & 63, wid = (threadIdx.x >> 6) % NW;
         __syncthreads();
         if (lane == 0) {
             lds[wid] = x;
@@ -61,13 +108,36 @@ __device__ __forceinline__ void block_sum2(double &x, double &y, double *lds)
     }
 }
 
-template <int BLOCK>
-__device__ __forceinline__ double block_max(double x, double *lds)
+template <int NW>
+__device__ __forceinline__ void group_sum(double &x, int &y, double *lds)
+{
+    x = wave_sum(x);
+    y = wave_sum(y);
+    if constexpr (NW > 1) {
+        const int lane = threadIdx.x & 63, wid = (threadIdx.x >> 6) % NW;
+        __syncthreads();
+        if (lane == 0) {
+            lds[wid] = x;
+            lds[NW + wid] = (double)y;
+        }
+        __syncthreads();
+        double sx = 0.0, sy = 0.0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            sx += lds[w];
+            sy += lds[NW + w];
+        }
+        x = sx;
+        y = (int)sy;
+    }
+}
+
+template <int NW>
+__device__ __forceinline__ double group_max(double x, double *lds)
 {
     x = wave_max(x);
-    if constexpr (BLOCK > 64) {
-        constexpr int NW = BLOCK / 64;
-        const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if constexpr (NW > 1) {
+        const int lane = threadIdx.x & 63, wid = (threadIdx.x >> 6) % NW;
         __syncthreads();
         if (lane == 0) lds[wid] = x;
         __syncthreads();
@@ -149,17 +219,19 @@ __global__ void init_kernel(Consts c, Bufs<T> b, double omega0)
 {
     const long long nm = c.ld * (long long)c.m, nn = c.ld * (long long)c.n;
     const long long stride = (long long)gridDim.x * blockDim.x;
-    for (long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x; x < nm; x += stride) {
+    const long long t0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    for (long long x = t0; x < nm; x += stride) {
         b.F[x] = T(0);
         b.Fhat[x] = T(0);
     }
-    for (long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x; x < nn; x += stride) {
+    for (long long x = t0; x < nn; x += stride) {
         const long long j = x / c.ld, i = x - j * c.ld;
         // Section 2.5 initialization: Y^0 = I - 1 1^T (0 on the diagonal, -1 off it); padding stays 0.
         b.Y[x] = (i < c.n && i != j) ? T(-1) : T(0);
         b.That[x] = 0.0;
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    for (long long x = t0; x < c.m; x += stride) b.mu[x] = 0.0;
+    if (t0 == 0) {
         DevScalars *sc = b.sc;
         sc->omega = omega0;
         sc->alpha = sc->eta / omega0;
@@ -178,56 +250,81 @@ __global__ void init_kernel(Consts c, Bufs<T> b, double omega0)
 }
 
 // -------------------------------------------------------------- edge phase
-// One workgroup per edge column; each thread keeps EPT entries of F[:,l] and q in
-// registers.  mu (Section 2.3, Section 2.6): if sum (q)_+ <= c the projection is (q)_+;
-// otherwise the active set S = {q_i > mu} and mu = (sum_S q - c)/|S| are iterated from
-// S = {q > 0}.  mu only grows and S only shrinks, so the loop ends when |S| stops
-// shrinking; the final mu is the exact value (sum_S q - c)/|S| on the support S.
-template <typename T, int BLOCK, int EPT, bool CHECK>
-__global__ __launch_bounds__(BLOCK) void edge_kernel(Consts c, Bufs<T> b, PartLayout pl)
+// WPE waves per edge column, each lane keeping EPT entries of F[:,l] and q in registers.
+// mu (Section 2.3, Section 2.6): mu = 0 if sum (q)_+ <= c; otherwise the support S and
+// mu = (sum_S q - c)/|S| satisfy S = {q > mu}.  Any mu' with S' = {q > mu'} nonempty
+// gives the lower bound (sum_{S'} q - c)/|S'| <= mu (the linear function it zeroes lies
+// below the convex piecewise-linear sum (q - x)_+ - c); from a lower bound the
+// active-set iteration S <- {q > mu}, mu <- (sum_S q - c)/|S| rises monotonically and
+// stops exactly when |S| stops shrinking.  The search starts from the larger of the
+// bounds given by S' = {q > 0} and S' = {q > mu of the previous iteration}, so a
+// column whose support did not move needs two block sums instead of five or six.
+template <typename T, int WPE, int EPT, bool CHECK, bool PARTIAL>
+__global__ __launch_bounds__(WPE == 1 ? 256 : 64 * WPE) void edge_kernel(Consts c, Bufs<T> b, PartLayout pl)
 {
-    __shared__ double lds[2 * (BLOCK / 64)];
+    constexpr int LANES = 64 * WPE;  // threads per edge column
+    __shared__ double lds[2 * WPE];
     if (b.sc->stop) return;
-    const int e = blockIdx.x;
+    const int e = WPE == 1 ? (int)blockIdx.x * 4 + (int)(threadIdx.x >> 6) : (int)blockIdx.x;
+    if (e >= c.m) return;  // whole waves only (WPE == 1): no block barrier follows
+    const int t = WPE == 1 ? (int)(threadIdx.x & 63) : (int)threadIdx.x;
     const int n = c.n;
     const long long ld = c.ld;
     const T ta = (T)b.sc->alpha;
     const T *yh = b.Y + (long long)b.head[e] * ld;
     const T *yt = b.Y + (long long)b.tail[e] * ld;
     T *f = b.F + (long long)e * ld;
+    const double cap = b.cap[e];
+    const double mu0 = b.mu[e];
     T fo[EPT], q[EPT];
-    double s = 0.0, cnt = 0.0;
 #pragma unroll
     for (int j = 0; j < EPT; ++j) {
-        const int i = threadIdx.x + j * BLOCK;
+        const int i = t + j * LANES;
         if (i < n) {
             fo[j] = f[i];
             q[j] = fo[j] + ta * (yh[i] - yt[i]);
-            if (q[j] > T(0)) {
-                s += (double)q[j];
-                cnt += 1.0;
-            }
         } else {
             fo[j] = T(0);
             q[j] = T(-1);  // never in the support
         }
     }
-    block_sum2<BLOCK>(s, cnt, lds);
-    const double cap = b.cap[e];
+    double sp = 0.0, sw = 0.0;
+    int cp = 0, cw = 0;
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+        const double qd = (double)q[j];
+        if (qd > 0.0) {
+            sp += qd;
+            ++cp;
+        }
+        if (qd > mu0) {
+            sw += qd;
+            ++cw;
+        }
+    }
+    group_sum<WPE>(sp, cp, lds);
+    group_sum<WPE>(sw, cw, lds);
     double mu = 0.0;
-    if (s > cap) {
-        mu = (s - cap) / cnt;
-        double prev = cnt;
+    if (sp > cap) {
+        mu = (sp - cap) / cp;
+        int prev = cp;  // mu came from S' = {q > 0}, a superset of {q > mu}
+        if (cw > 0) {
+            const double mw = (sw - cap) / cw;
+            if (mw > mu) {
+                mu = mw;
+                prev = mw >= mu0 ? cw : 0x7fffffff;  // {q > mu0} contains {q > mw} only if mw >= mu0
+            }
+        }
         for (int pass = 0; pass <= n; ++pass) {
-            s = 0.0;
-            cnt = 0.0;
+            double s = 0.0;
+            int cnt = 0;
 #pragma unroll
             for (int j = 0; j < EPT; ++j)
                 if ((double)q[j] > mu) {
                     s += (double)q[j];
-                    cnt += 1.0;
+                    ++cnt;
                 }
-            block_sum2<BLOCK>(s, cnt, lds);
+            group_sum<WPE>(s, cnt, lds);
             if (cnt >= prev) break;
             mu = (s - cap) / cnt;
             prev = cnt;
@@ -238,15 +335,17 @@ __global__ __launch_bounds__(BLOCK) void edge_kernel(Consts c, Bufs<T> b, PartLa
     double dsum = 0.0, esum = 0.0, gmax = -INFINITY;
 #pragma unroll
     for (int j = 0; j < EPT; ++j) {
-        const int i = threadIdx.x + j * BLOCK;
+        const int i = t + j * LANES;
         if (i < n) {
             const double fod = (double)fo[j];
             const double fh = fmax((double)q[j] - mu, 0.0);
             const T fn = (T)(rho * fh + omr * fod);
             f[i] = fn;
             fb[i] = (T)(2.0 * fh - fod);
-            const double d = (double)fn - fod;
-            dsum += d * d;
+            if (PARTIAL) {
+                const double d = (double)fn - fod;
+                dsum += d * d;
+            }
             if (CHECK) {
                 b.Fhat[(long long)e * ld + i] = (T)fh;
                 const T dd = (T)(fh - (double)q[j]);
@@ -256,10 +355,11 @@ __global__ __launch_bounds__(BLOCK) void edge_kernel(Consts c, Bufs<T> b, PartLa
             }
         }
     }
-    block_sum2<BLOCK>(dsum, esum, lds);
-    if (CHECK) gmax = block_max<BLOCK>(gmax, lds);
-    if (threadIdx.x == 0) {
-        b.part[pl.dF + e] = dsum;
+    if (PARTIAL) group_sum<WPE>(dsum, esum, lds);
+    if (CHECK) gmax = group_max<WPE>(gmax, lds);
+    if (t == 0) {
+        b.mu[e] = mu;
+        if (PARTIAL) b.part[pl.dF + e] = dsum;
         if (CHECK) {
             b.part[pl.e + e] = esum;
             b.part[pl.sup + e] = cap * fmax(gmax, 0.0);  // c_l (max_i (Y A)_il)_+
@@ -268,37 +368,63 @@ __global__ __launch_bounds__(BLOCK) void edge_kernel(Consts c, Bufs<T> b, PartLa
 }
 
 // -------------------------------------------------------------- node phase
-// Grid (ceil(n/NODE_BLOCK), n): thread (x, j) owns entry i of node column j.
-// V_ij = sum_{l in in(j)} Fbar_il - sum_{l in out(j)} Fbar_il, in CSR order, FP64.
-template <typename T, int UTIL, bool CHECK>
-__global__ __launch_bounds__(NODE_BLOCK) void node_kernel(Consts c, Bufs<T> b, PartLayout pl)
+// Grid (ceil(n/NB), n): thread (x, j) owns entry i of node column j.
+// V_ij = sum_{l in in(j)} Fbar_il - sum_{l in out(j)} Fbar_il, accumulated in FP64 in CSR
+// order; loads are issued eight edges at a time, the additions stay in list order.
+template <typename T, int NB>
+__device__ __forceinline__ double gather_in_minus_out(const T *X, const int *in_edge, int i0, int i1, int o0, int o1,
+                                                     long long ld, int i)
 {
-    __shared__ double lds[2 * (NODE_BLOCK / 64)];
+    double v = 0.0;
+    int k = i0;
+    for (; k + 8 <= i1; k += 8) {
+        T a[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a[u] = X[(long long)in_edge[k + u] * ld + i];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v += (double)a[u];
+    }
+    for (; k < i1; ++k) v += (double)X[(long long)in_edge[k] * ld + i];
+    int e = o0;
+    for (; e + 8 <= o1; e += 8) {
+        T a[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a[u] = X[(long long)(e + u) * ld + i];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v -= (double)a[u];
+    }
+    for (; e < o1; ++e) v -= (double)X[(long long)e * ld + i];
+    return v;
+}
+
+template <typename T, int NB, int UTIL, bool CHECK, bool PARTIAL>
+__global__ __launch_bounds__(NB) void node_kernel(Consts c, Bufs<T> b, PartLayout pl)
+{
+    constexpr int NW = NB / 64;
+    __shared__ double lds[2 * NW];
     if (b.sc->stop) return;
     const int j = blockIdx.y;
-    const int i = blockIdx.x * NODE_BLOCK + threadIdx.x;
+    const int i = blockIdx.x * NB + threadIdx.x;
     const int blk = blockIdx.y * gridDim.x + blockIdx.x;
     const long long ld = c.ld;
     const double beta = b.sc->beta, g = c.gamma;
     double dy2 = 0.0, p = 0.0, conj = 0.0, rnum = 0.0, rden = 0.0, nonpos = 0.0, yinf = 0.0;
     if (i < c.n) {
         const int i0 = b.in_off[j], i1 = b.in_off[j + 1], o0 = b.out_off[j], o1 = b.out_off[j + 1];
-        double v = 0.0;
-        for (int k = i0; k < i1; ++k) v += (double)b.Fbar[(long long)b.in_edge[k] * ld + i];
-        for (int e = o0; e < o1; ++e) v -= (double)b.Fbar[(long long)e * ld + i];
+        const double v = gather_in_minus_out<T, NB>(b.Fbar, b.in_edge, i0, i1, o0, o1, ld, i);
         const long long x = (long long)j * ld + i;
         const double y = (double)b.Y[x];
         const double w = (double)b.W[x];
         const double yhat = (i != j) ? prox_dual<UTIL>(y - beta * v, beta, w, g, c.c1) : 0.0;
         const T yn = (T)(c.rho * yhat + (1.0 - c.rho) * y);
         b.Y[x] = yn;
-        const double d = (double)yn - y;
-        dy2 = d * d;
+        if (PARTIAL) {
+            const double d = (double)yn - y;
+            dy2 = d * d;
+        }
         if (CHECK) {
             // T = -Fhat A^T, U' = u'(T), and the pieces of p, d and rel_primal (with Y^k = y).
-            double t = 0.0;
-            for (int k = i0; k < i1; ++k) t -= (double)b.Fhat[(long long)b.in_edge[k] * ld + i];
-            for (int e = o0; e < o1; ++e) t += (double)b.Fhat[(long long)e * ld + i];
+            const double t = -gather_in_minus_out<T, NB>(b.Fhat, b.in_edge, i0, i1, o0, o1, ld, i);
             b.That[x] = t;
             double up = 0.0;
             if (i != j) {
@@ -320,15 +446,17 @@ __global__ __launch_bounds__(NODE_BLOCK) void node_kernel(Consts c, Bufs<T> b, P
             b.Up[x] = up;
         }
     }
-    double zero = 0.0;
-    block_sum2<NODE_BLOCK>(dy2, zero, lds);
+    if (PARTIAL) {
+        double zero = 0.0;
+        group_sum<NW>(dy2, zero, lds);
+    }
     if (CHECK) {
-        block_sum2<NODE_BLOCK>(p, conj, lds);
-        block_sum2<NODE_BLOCK>(rnum, rden, lds);
-        block_sum2<NODE_BLOCK>(nonpos, yinf, lds);
+        group_sum<NW>(p, conj, lds);
+        group_sum<NW>(rnum, rden, lds);
+        group_sum<NW>(nonpos, yinf, lds);
     }
     if (threadIdx.x == 0) {
-        b.part[pl.dY + blk] = dy2;
+        if (PARTIAL) b.part[pl.dY + blk] = dy2;
         if (CHECK) {
             b.part[pl.p + blk] = p;
             b.part[pl.conj + blk] = conj;
@@ -342,24 +470,27 @@ __global__ __launch_bounds__(NODE_BLOCK) void node_kernel(Consts c, Bufs<T> b, P
 
 // ---------------------------------------------------------- residual pass
 // Per edge: G[:,l] = U'[:,head] - U'[:,tail]; partials ||G_l||^2 and <G_l, D_l>.
-template <typename T, int BLOCK>
-__global__ __launch_bounds__(BLOCK) void residual_kernel(Consts c, Bufs<T> b, PartLayout pl)
+// One wave per edge, four edges per 256-thread block.
+template <typename T>
+__global__ __launch_bounds__(256) void residual_kernel(Consts c, Bufs<T> b, PartLayout pl)
 {
-    __shared__ double lds[2 * (BLOCK / 64)];
     if (b.sc->stop) return;
-    const int e = blockIdx.x;
+    const int e = (int)blockIdx.x * 4 + (int)(threadIdx.x >> 6);
+    if (e >= c.m) return;
+    const int lane = threadIdx.x & 63;
     const long long ld = c.ld;
     const double *uh = b.Up + (long long)b.head[e] * ld;
     const double *ut = b.Up + (long long)b.tail[e] * ld;
     const T *d = b.D + (long long)e * ld;
     double a = 0.0, bb = 0.0;
-    for (int i = threadIdx.x; i < c.n; i += BLOCK) {
+    for (int i = lane; i < c.n; i += 64) {
         const double gg = uh[i] - ut[i];
         a += gg * gg;
         bb += gg * (double)d[i];
     }
-    block_sum2<BLOCK>(a, bb, lds);
-    if (threadIdx.x == 0) {
+    a = wave_sum(a);
+    bb = wave_sum(bb);
+    if (lane == 0) {
         b.part[pl.a + e] = a;
         b.part[pl.b + e] = bb;
     }
@@ -373,12 +504,13 @@ __device__ double seg_sum(const double *p, long long len, double *lds)
     double s = 0.0;
     for (long long x = threadIdx.x; x < len; x += CTRL_BLOCK) s += p[x];
     double z = 0.0;
-    block_sum2<CTRL_BLOCK>(s, z, lds);
+    group_sum<CTRL_BLOCK / 64>(s, z, lds);
     return s;
 }
 
 template <typename T>
-__global__ __launch_bounds__(CTRL_BLOCK) void control_kernel(Consts c, Bufs<T> b, PartLayout pl, int check)
+__global__ __launch_bounds__(CTRL_BLOCK) void control_kernel(Consts c, Bufs<T> b, PartLayout pl, int check,
+                                                              int adapt, long long k_after)
 {
     __shared__ double lds[2 * (CTRL_BLOCK / 64)];
     DevScalars *sc = b.sc;
@@ -439,16 +571,15 @@ __global__ __launch_bounds__(CTRL_BLOCK) void control_kernel(Consts c, Bufs<T> b
     } else {
         sc->checked = 0;
     }
-    const long long k = sc->k;
     const bool bad = !isfinite(dF) || !isfinite(dY);
     // Algorithm 2.1 step 3, (e-primal_weight)
-    if (!bad && c.k_adapt > 0 && k % c.k_adapt == 0 && dF > c.tau && dY > c.tau) {
+    if (!bad && adapt && dF > c.tau && dY > c.tau) {
         const double om = pow(dY / dF, c.theta) * pow(sc->omega, 1.0 - c.theta);
         sc->omega = om;
         sc->alpha = sc->eta / om;
         sc->beta = sc->eta * om;
     }
-    sc->k = k + 1;
+    sc->k = k_after;
     if (bad) {
         sc->state = 3;
         sc->stop = 1;
@@ -468,16 +599,18 @@ __global__ void poison_kernel(Bufs<T> b, int which, long long off)
 // ---------------------------------------------------------------- launchers
 EdgeShape edge_shape_for(int n)
 {
-    if (n <= 64) return {64, 1};
-    if (n <= 128) return {64, 2};
-    if (n <= 256) return {64, 4};
-    if (n <= 512) return {128, 4};
-    if (n <= 1024) return {256, 4};
-    if (n <= 2048) return {256, 8};
-    if (n <= 4096) return {512, 8};
-    if (n <= 8192) return {512, 16};
-    return {1024, 16};
+    if (n <= 64) return {1, 1};
+    if (n <= 128) return {1, 2};
+    if (n <= 256) return {1, 4};
+    if (n <= 512) return {2, 4};
+    if (n <= 1024) return {4, 4};
+    if (n <= 2048) return {4, 8};
+    if (n <= 4096) return {8, 8};
+    if (n <= 8192) return {8, 16};
+    return {8, 32};
 }
+
+int node_block_for(int n) { return n <= 512 ? 64 : 256; }
 
 template <typename T>
 hipError_t launch_init(const Consts &c, const Bufs<T> &b, double omega0, hipStream_t st)
@@ -486,60 +619,74 @@ hipError_t launch_init(const Consts &c, const Bufs<T> &b, double omega0, hipStre
     return hipGetLastError();
 }
 
-template <typename T, int BLOCK, int EPT>
-static void edge_go(const Consts &c, const Bufs<T> &b, const PartLayout &pl, bool check, hipStream_t st)
+template <typename T, int WPE, int EPT>
+static void edge_go(const Consts &c, const Bufs<T> &b, const PartLayout &pl, bool check, bool partial,
+                    hipStream_t st)
 {
+    const dim3 grid(WPE == 1 ? (c.m + 3) / 4 : c.m), block(WPE == 1 ? 256 : 64 * WPE);
     if (check)
-        hipLaunchKernelGGL((edge_kernel<T, BLOCK, EPT, true>), dim3(c.m), dim3(BLOCK), 0, st, c, b, pl);
+        hipLaunchKernelGGL((edge_kernel<T, WPE, EPT, true, true>), grid, block, 0, st, c, b, pl);
+    else if (partial)
+        hipLaunchKernelGGL((edge_kernel<T, WPE, EPT, false, true>), grid, block, 0, st, c, b, pl);
     else
-        hipLaunchKernelGGL((edge_kernel<T, BLOCK, EPT, false>), dim3(c.m), dim3(BLOCK), 0, st, c, b, pl);
+        hipLaunchKernelGGL((edge_kernel<T, WPE, EPT, false, false>), grid, block, 0, st, c, b, pl);
 }
 
 template <typename T>
 hipError_t launch_edge(const Consts &c, const Bufs<T> &b, const PartLayout &pl, EdgeShape sh, bool check,
-                       hipStream_t st)
+                       bool partial, hipStream_t st)
 {
-#define MCF_EDGE_CASE(B, E) \
-    if (sh.block == B && sh.ept == E) { edge_go<T, B, E>(c, b, pl, check, st); return hipGetLastError(); }
-    MCF_EDGE_CASE(64, 1)
-    MCF_EDGE_CASE(64, 2)
-    MCF_EDGE_CASE(64, 4)
-    MCF_EDGE_CASE(128, 4)
-    MCF_EDGE_CASE(256, 4)
-    MCF_EDGE_CASE(256, 8)
-    MCF_EDGE_CASE(512, 8)
-    MCF_EDGE_CASE(512, 16)
-    MCF_EDGE_CASE(1024, 16)
+#define MCF_EDGE_CASE(W, E) \
+    if (sh.wpe == W && sh.ept == E) { edge_go<T, W, E>(c, b, pl, check, partial, st); return hipGetLastError(); }
+    MCF_EDGE_CASE(1, 1)
+    MCF_EDGE_CASE(1, 2)
+    MCF_EDGE_CASE(1, 4)
+    MCF_EDGE_CASE(2, 4)
+    MCF_EDGE_CASE(4, 4)
+    MCF_EDGE_CASE(4, 8)
+    MCF_EDGE_CASE(8, 8)
+    MCF_EDGE_CASE(8, 16)
+    MCF_EDGE_CASE(8, 32)
 #undef MCF_EDGE_CASE
     return hipErrorInvalidValue;
 }
 
-template <typename T>
-hipError_t launch_node(const Consts &c, const Bufs<T> &b, const PartLayout &pl, bool check, hipStream_t st)
+template <typename T, int NB, int UTIL>
+static void node_go(const Consts &c, const Bufs<T> &b, const PartLayout &pl, bool check, bool partial, hipStream_t st)
 {
-    const dim3 grid((c.n + NODE_BLOCK - 1) / NODE_BLOCK, c.n);
-    if (c.utility == 0) {
-        if (check) hipLaunchKernelGGL((node_kernel<T, 0, true>), grid, dim3(NODE_BLOCK), 0, st, c, b, pl);
-        else hipLaunchKernelGGL((node_kernel<T, 0, false>), grid, dim3(NODE_BLOCK), 0, st, c, b, pl);
+    const dim3 grid((c.n + NB - 1) / NB, c.n);
+    if (check) hipLaunchKernelGGL((node_kernel<T, NB, UTIL, true, true>), grid, dim3(NB), 0, st, c, b, pl);
+    else if (partial) hipLaunchKernelGGL((node_kernel<T, NB, UTIL, false, true>), grid, dim3(NB), 0, st, c, b, pl);
+    else hipLaunchKernelGGL((node_kernel<T, NB, UTIL, false, false>), grid, dim3(NB), 0, st, c, b, pl);
+}
+
+template <typename T>
+hipError_t launch_node(const Consts &c, const Bufs<T> &b, const PartLayout &pl, bool check, bool partial,
+                       hipStream_t st)
+{
+    if (c.node_block == 64) {
+        if (c.utility == 0) node_go<T, 64, 0>(c, b, pl, check, partial, st);
+        else node_go<T, 64, 1>(c, b, pl, check, partial, st);
     } else {
-        if (check) hipLaunchKernelGGL((node_kernel<T, 1, true>), grid, dim3(NODE_BLOCK), 0, st, c, b, pl);
-        else hipLaunchKernelGGL((node_kernel<T, 1, false>), grid, dim3(NODE_BLOCK), 0, st, c, b, pl);
+        if (c.utility == 0) node_go<T, 256, 0>(c, b, pl, check, partial, st);
+        else node_go<T, 256, 1>(c, b, pl, check, partial, st);
     }
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_residual(const Consts &c, const Bufs<T> &b, const PartLayout &pl, EdgeShape sh, hipStream_t st)
+hipError_t launch_residual(const Consts &c, const Bufs<T> &b, const PartLayout &pl, EdgeShape, hipStream_t st)
 {
-    if (sh.block <= 64) hipLaunchKernelGGL((residual_kernel<T, 64>), dim3(c.m), dim3(64), 0, st, c, b, pl);
-    else hipLaunchKernelGGL((residual_kernel<T, 256>), dim3(c.m), dim3(256), 0, st, c, b, pl);
+    hipLaunchKernelGGL(residual_kernel<T>, dim3((c.m + 3) / 4), dim3(256), 0, st, c, b, pl);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_control(const Consts &c, const Bufs<T> &b, const PartLayout &pl, bool check, hipStream_t st)
+hipError_t launch_control(const Consts &c, const Bufs<T> &b, const PartLayout &pl, bool check, bool adapt,
+                          long long k_after, hipStream_t st)
 {
-    hipLaunchKernelGGL(control_kernel<T>, dim3(1), dim3(CTRL_BLOCK), 0, st, c, b, pl, check ? 1 : 0);
+    hipLaunchKernelGGL(control_kernel<T>, dim3(1), dim3(CTRL_BLOCK), 0, st, c, b, pl, check ? 1 : 0, adapt ? 1 : 0,
+                       k_after);
     return hipGetLastError();
 }
 
@@ -550,15 +697,16 @@ hipError_t launch_poison(const Bufs<T> &b, int which, long long offset, hipStrea
     return hipGetLastError();
 }
 
-#define MCF_INSTANTIATE(T)                                                                                  \
-    template hipError_t launch_init<T>(const Consts &, const Bufs<T> &, double, hipStream_t);               \
-    template hipError_t launch_edge<T>(const Consts &, const Bufs<T> &, const PartLayout &, EdgeShape, bool, \
-                                       hipStream_t);                                                        \
-    template hipError_t launch_node<T>(const Consts &, const Bufs<T> &, const PartLayout &, bool, hipStream_t); \
-    template hipError_t launch_residual<T>(const Consts &, const Bufs<T> &, const PartLayout &, EdgeShape,   \
-                                           hipStream_t);                                                    \
-    template hipError_t launch_control<T>(const Consts &, const Bufs<T> &, const PartLayout &, bool,         \
-                                          hipStream_t);                                                     \
+#define MCF_INSTANTIATE(T)                                                                                      \
+    template hipError_t launch_init<T>(const Consts &, const Bufs<T> &, double, hipStream_t);                   \
+    template hipError_t launch_edge<T>(const Consts &, const Bufs<T> &, const PartLayout &, EdgeShape, bool,     \
+                                       bool, hipStream_t);                                                      \
+    template hipError_t launch_node<T>(const Consts &, const Bufs<T> &, const PartLayout &, bool, bool,          \
+                                       hipStream_t);                                                            \
+    template hipError_t launch_residual<T>(const Consts &, const Bufs<T> &, const PartLayout &, EdgeShape,       \
+                                           hipStream_t);                                                        \
+    template hipError_t launch_control<T>(const Consts &, const Bufs<T> &, const PartLayout &, bool, bool,       \
+                                          long long, hipStream_t);                                              \
     template hipError_t launch_poison<T>(const Bufs<T> &, int, long long, hipStream_t);
 
 MCF_INSTANTIATE(float)

@@ -21,7 +21,11 @@ size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
 long long padded_ld(int n) { return (long long)((n + 63) / 64) * 64; }
 
-int node_blocks(int n) { return ((n + NODE_BLOCK - 1) / NODE_BLOCK) * n; }
+int node_blocks(int n)
+{
+    const int nb = node_block_for(n);
+    return ((n + nb - 1) / nb) * n;
+}
 
 PartLayout part_layout(int m, int nb)
 {
@@ -45,7 +49,7 @@ PartLayout part_layout(int m, int nb)
 
 // Byte offsets of every device buffer inside one allocation.
 struct Plan {
-    size_t F, Fbar, Fhat, D, Y, W, That, Up, cap, tail, head, out_off, in_off, in_edge, part, sc, total;
+    size_t F, Fbar, Fhat, D, Y, W, That, Up, cap, mu, tail, head, out_off, in_off, in_edge, part, sc, total;
 };
 
 Plan make_plan(int n, int m, int precision)
@@ -66,6 +70,7 @@ Plan make_plan(int n, int m, int precision)
     p.That = take(nn * 8);
     p.Up = take(nn * 8);
     p.cap = take((size_t)m * 8);
+    p.mu = take((size_t)m * 8);
     p.tail = take((size_t)m * 4);
     p.head = take((size_t)m * 4);
     p.out_off = take((size_t)(n + 1) * 4);
@@ -94,6 +99,7 @@ struct mcf_solver {
     bool own_stream = false;
     DevScalars *hs = nullptr;  // pinned host mirror of the device scalars
     int state = MCF_RUNNING;
+    long long k = 0;  // PDHG iterations completed (authoritative count)
     double seconds = 0.0;
     // kernel timing of the edge phase
     bool timing = false;
@@ -120,6 +126,7 @@ struct mcf_solver {
         b.in_off = (const int *)(base + plan.in_off);
         b.in_edge = (const int *)(base + plan.in_edge);
         b.cap = (const double *)(base + plan.cap);
+        b.mu = (double *)(base + plan.mu);
         b.part = (double *)(base + plan.part);
         b.sc = (DevScalars *)(base + plan.sc);
         return b;
@@ -231,6 +238,7 @@ int do_reset(mcf_solver *s)
     MCF_TRY(hipMemcpyAsync(s->hs, s->dsc(), sizeof(DevScalars), hipMemcpyDeviceToHost, s->stream));
     MCF_TRY(hipStreamSynchronize(s->stream));
     s->state = MCF_RUNNING;
+    s->k = 0;
     return MCF_OK;
 }
 
@@ -272,13 +280,19 @@ int collect_events(mcf_solver *s)
     return MCF_OK;
 }
 
-// Enqueues `count` iterations; only the last one is a check iteration.
+// Enqueues `count` iterations starting at iteration s->k; only the last one is a check
+// iteration.  Iterations that adapt omega (k a multiple of k_adapt) or check the residual
+// write step-norm partials and end in a control launch; the others are two launches.
 template <typename T>
 int enqueue_block(mcf_solver *s, long long count)
 {
     const Bufs<T> b = s->bufs<T>();
+    const int ka = s->opt.k_adapt;
     for (long long it = 0; it < count; ++it) {
+        const long long k = s->k + it;
         const bool check = it == count - 1;
+        const bool adapt = ka > 0 && k % ka == 0;
+        const bool partial = check || adapt;
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (s->timing) {
             e0 = next_event(s);
@@ -286,11 +300,11 @@ int enqueue_block(mcf_solver *s, long long count)
             if (!e0 || !e1) return MCF_E_DEVICE;
             MCF_TRY(hipEventRecord(e0, s->stream));
         }
-        MCF_TRY(launch_edge<T>(s->c, b, s->pl, s->sh, check, s->stream));
+        MCF_TRY(launch_edge<T>(s->c, b, s->pl, s->sh, check, partial, s->stream));
         if (s->timing) MCF_TRY(hipEventRecord(e1, s->stream));
-        MCF_TRY(launch_node<T>(s->c, b, s->pl, check, s->stream));
+        MCF_TRY(launch_node<T>(s->c, b, s->pl, check, partial, s->stream));
         if (check) MCF_TRY(launch_residual<T>(s->c, b, s->pl, s->sh, s->stream));
-        MCF_TRY(launch_control<T>(s->c, b, s->pl, check, s->stream));
+        if (partial) MCF_TRY(launch_control<T>(s->c, b, s->pl, check, adapt, k + 1, s->stream));
     }
     return MCF_OK;
 }
@@ -314,14 +328,16 @@ int drive(mcf_solver *s, long long target, bool stop_test)
             s->state = s->hs->state == MCF_DIVERGED ? MCF_DIVERGED : MCF_CONVERGED;
             break;
         }
-        if (s->hs->k >= target) {
+        if (s->k >= target) {
             s->state = stop_test ? MCF_MAX_ITER : MCF_RUNNING;
             break;
         }
-        const long long count = std::min(K, target - s->hs->k);
+        const long long count = std::min(K, target - s->k);
         rc = s->precision == MCF_FP32 ? enqueue_block<float>(s, count) : enqueue_block<double>(s, count);
         if (rc) return rc;
         if ((rc = pull_scalars(s))) return rc;
+        // a stop raised inside the block skipped the launches after it
+        s->k = s->hs->stop ? s->hs->k : s->k + count;
         if (s->timing && (rc = collect_events(s))) return rc;
     }
     s->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -473,6 +489,7 @@ int mcf_create(int32_t n, int32_t m, const int32_t *tail, const int32_t *head, c
     c.k_adapt = o.k_adapt;
     c.stop_rule = o.stop_rule;
     c.nblk_node = node_blocks(n);
+    c.node_block = node_block_for(n);
 
     int rc = MCF_OK;
     if (hipSetDevice(o.device) != hipSuccess) rc = MCF_E_DEVICE;
@@ -532,7 +549,7 @@ int mcf_run(mcf_solver *s, int64_t iters)
         s->hs->stop = 0;
         if ((rc = push_scalars(s))) return rc;
     }
-    return drive(s, s->hs->k + iters, false);
+    return drive(s, s->k + iters, false);
 }
 
 int mcf_status(const mcf_solver *s, mcf_result *r)
@@ -542,7 +559,7 @@ int mcf_status(const mcf_solver *s, mcf_result *r)
     std::memset(r, 0, sizeof(*r));
     r->state = s->state;
     r->checked = h.checked;
-    r->iters = h.k;
+    r->iters = s->k;
     r->r = h.r;
     r->r_paper = h.r_paper;
     r->rel_primal = h.rel_primal;
@@ -579,7 +596,7 @@ int mcf_get_state(mcf_solver *s, double *F, double *Y, mcf_scalars *sc)
     if (Y && (rc = download_any(s, s->plan.Y, s->n, false, Y))) return rc;
     if (sc) {
         if ((rc = pull_scalars(s))) return rc;
-        sc->k = s->hs->k;
+        sc->k = s->k;
         sc->omega = s->hs->omega;
     }
     return MCF_OK;
@@ -594,6 +611,7 @@ int mcf_set_state(mcf_solver *s, const double *F, const double *Y, const mcf_sca
     if (rc) return rc;
     if ((rc = pull_scalars(s))) return rc;
     if (sc) {
+        s->k = sc->k;
         s->hs->k = sc->k;
         s->hs->omega = sc->omega;
         s->hs->alpha = s->hs->eta / sc->omega;
@@ -652,7 +670,7 @@ int mcf_layout(const mcf_solver *s, int32_t *ld, int32_t *edge_block, int32_t *e
 {
     if (!s) return MCF_E_ARG;
     if (ld) *ld = (int32_t)s->ld;
-    if (edge_block) *edge_block = s->sh.block;
+    if (edge_block) *edge_block = 64 * s->sh.wpe;
     if (edge_ept) *edge_ept = s->sh.ept;
     return MCF_OK;
 }
