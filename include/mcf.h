@@ -43,6 +43,10 @@ enum { MCF_FP64 = 0, MCF_FP32 = 1 };                     /* precision of F, Y; r
 enum { MCF_STOP_REL_KKT = 0, MCF_STOP_PAPER = 1 };       /* rel_kkt <= tol  |  r^k < n m tol (Algorithm 2.1) */
 enum { MCF_OK = 0, MCF_E_ARG = -1, MCF_E_GRAPH = -2, MCF_E_NOMEM = -3, MCF_E_DEVICE = -4, MCF_E_STATE = -5 };
 enum { MCF_RUNNING = 0, MCF_CONVERGED = 1, MCF_MAX_ITER = 2, MCF_DIVERGED = 3 }; /* solve states, not errors */
+/* Kernel organisation of one iteration.  TWO_PHASE: an edge-phase launch then a node-phase
+ * launch.  FUSED (n <= 512 only): one launch in which each node's workgroup projects every
+ * edge incident to it.  Both compute the same iteration; AUTO picks FUSED when n <= 512. */
+enum { MCF_KERNELS_AUTO = 0, MCF_KERNELS_TWO_PHASE = 1, MCF_KERNELS_FUSED = 2 };
 
 /* Solver options.  Defaults (mcf_options_default) are the paper's parameters:
  * rho = 1.9 (Section 2.2), theta = 0.5, k_adapt = 100, tau = 1e-5, omega0 = 1 (Section 2.4). */
@@ -55,7 +59,7 @@ typedef struct {
     int32_t k_adapt;        /* adapt omega when k is a multiple of k_adapt (k = 0 included); <= 0 disables */
     double rho, theta, tau, omega0;
     int32_t device;         /* HIP device ordinal */
-    int32_t reserved0;
+    int32_t kernel_mode;    /* MCF_KERNELS_AUTO (fused for n <= 512), MCF_KERNELS_TWO_PHASE or MCF_KERNELS_FUSED */
     void *stream;           /* hipStream_t to run on, or NULL for a stream owned by the handle */
     void *workspace;        /* optional caller device memory (>= mcf_workspace_bytes), or NULL */
     size_t workspace_bytes;
@@ -88,12 +92,12 @@ typedef struct {
  * k_adapt 100, rho 1.9, theta 0.5, tau 1e-5, omega0 1, device 0, no stream, no workspace. */
 void mcf_options_default(mcf_options *o);
 
-/* Device bytes one instance needs at this precision (buffers, CSR lists, partials).
- * Returns 0 if n or m is out of range. */
+/* Device bytes one instance needs at this precision with the kernel organisation AUTO picks
+ * (buffers, CSR lists, partials).  Returns 0 if n or m is out of range. */
 size_t mcf_workspace_bytes(int32_t n, int32_t m, int32_t precision);
 
 /* Builds an instance and sets the cold start of Section 2.5 (F = 0, Y = I - 1 1^T, omega = omega0).
- *   n, m       nodes (2 <= n <= 32768) and edges (m >= 1);
+ *   n, m       nodes (2 <= n <= 16384) and edges (m >= 1);
  *   tail, head m edge endpoints in [0, n), tail != head (parallel edges allowed);
  *   cap        m capacities c_l > 0 (Section 1.1);
  *   utility    MCF_UTIL_LOG or MCF_UTIL_POWER; gamma in (0, 1) for POWER (ignored for LOG);
@@ -147,8 +151,9 @@ int mcf_debug_poison(mcf_solver *s, int32_t which, int64_t index);
 int mcf_enable_kernel_timing(mcf_solver *s, int32_t enable);
 int mcf_kernel_time(mcf_solver *s, double *edge_ms, int64_t *edge_launches);
 
-/* Internal sizes chosen at create: padded leading dimension and threads per edge column. */
-int mcf_layout(const mcf_solver *s, int32_t *ld, int32_t *edge_block, int32_t *edge_ept);
+/* Internal sizes chosen at create: padded leading dimension, threads per edge column,
+ * entries per thread, and the kernel organisation in use (MCF_KERNELS_TWO_PHASE or _FUSED). */
+int mcf_layout(const mcf_solver *s, int32_t *ld, int32_t *edge_block, int32_t *edge_ept, int32_t *kernel_mode);
 
 #ifdef __cplusplus
 }

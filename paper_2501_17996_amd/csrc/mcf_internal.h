@@ -30,7 +30,12 @@ struct Consts {
     int k_adapt, stop_rule;
     int nblk_node;         // node-phase blocks (partials per quantity)
     int node_block;        // threads per node-phase block (64 or 256)
+    int fused;             // 1: node-centric single-launch iteration (n <= FUSED_MAX_N)
+    int nep, nnp;          // partials per edge quantity (dF, e, sup) and per node quantity
 };
+
+// Largest n served by the node-centric fused iteration (one wave per edge column).
+constexpr int FUSED_MAX_N = 512;
 
 // Offsets (in doubles) of the partial-sum segments.
 struct PartLayout {
@@ -39,9 +44,13 @@ struct PartLayout {
     long long total;
 };
 
+// Device buffers of one instance.  In fused mode F, Y and mu ping-pong with F2, Y2,
+// mu2: iteration k reads the buffers of parity (k + parity offset) & 1 and writes the others.
 template <typename T>
 struct Bufs {
     T *F, *Fbar, *Fhat, *D, *Y, *W;
+    T *F2, *Y2;
+    double *mu2;
     double *That, *Up;
     const int *tail, *head, *out_off, *in_off, *in_edge;
     const double *cap;
@@ -67,6 +76,9 @@ hipError_t launch_edge(const Consts &c, const Bufs<T> &b, const PartLayout &pl, 
 template <typename T>
 hipError_t launch_node(const Consts &c, const Bufs<T> &b, const PartLayout &pl, bool check, bool partial,
                        hipStream_t st);
+template <typename T>
+hipError_t launch_fused(const Consts &c, const Bufs<T> &b, const PartLayout &pl, EdgeShape sh, int parity,
+                        bool check, bool partial, hipStream_t st);
 template <typename T>
 hipError_t launch_residual(const Consts &c, const Bufs<T> &b, const PartLayout &pl, EdgeShape sh,
                            hipStream_t st);

@@ -468,6 +468,199 @@ __global__ __launch_bounds__(NB) void node_kernel(Consts c, Bufs<T> b, PartLayou
     }
 }
 
+// ----------------------------------------------------- fused node iteration
+// For n <= 64*EPT <= FUSED_MAX_N one PDHG iteration is a single launch: workgroup j
+// (four waves) recomputes, one wave per column, the projection of every edge incident
+// to node j (an edge is projected by both of its end nodes, from identical inputs with
+// identical code, so both get the same bits), accumulates V[:,j] = sum_in Fbar - sum_out
+// Fbar in registers, adds the four waves' sums in wave order through LDS, and updates
+// Y[:,j].  The tail's workgroup writes the edge's new F column and multiplier.  F, Y and
+// mu are read from one buffer set and written to the other, so no workgroup can see a
+// value of the iteration in flight.
+template <typename T, int EPT, int UTIL, bool CHECK, bool PARTIAL>
+__global__ __launch_bounds__(256) void fused_kernel(Consts c, Bufs<T> b, PartLayout pl, int parity)
+{
+    __shared__ double vsh[(CHECK ? 2 : 1) * 4 * EPT * 64];
+    __shared__ double red[8];
+    if (b.sc->stop) return;
+    const int j = blockIdx.x;
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int n = c.n;
+    const long long ld = c.ld;
+    const T *Fc = parity ? b.F2 : b.F;
+    T *Fn = parity ? b.F : b.F2;
+    const T *Yc = parity ? b.Y2 : b.Y;
+    T *Yn = parity ? b.Y : b.Y2;
+    const double *muc = parity ? b.mu2 : b.mu;
+    double *mun = parity ? b.mu : b.mu2;
+    const T ta = (T)b.sc->alpha;
+    const double beta = b.sc->beta, g = c.gamma, rho = c.rho, omr = 1.0 - c.rho;
+    const int i0 = b.in_off[j], din = b.in_off[j + 1] - i0;
+    const int o0 = b.out_off[j], deg = din + (b.out_off[j + 1] - o0);
+    double vacc[EPT], tacc[EPT];
+#pragma unroll
+    for (int jj = 0; jj < EPT; ++jj) vacc[jj] = tacc[jj] = 0.0;
+    double dsum = 0.0, esum = 0.0, supsum = 0.0;
+    for (int idx = wv; idx < deg; idx += 4) {
+        const bool out = idx >= din;
+        const int e = out ? o0 + (idx - din) : b.in_edge[i0 + idx];
+        const T *yh = Yc + (long long)b.head[e] * ld;
+        const T *yt = Yc + (long long)b.tail[e] * ld;
+        const T *f = Fc + (long long)e * ld;
+        const double cap = b.cap[e], mu0 = muc[e];
+        T fo[EPT], q[EPT];
+#pragma unroll
+        for (int jj = 0; jj < EPT; ++jj) {
+            const int i = lane + jj * 64;
+            if (i < n) {
+                fo[jj] = f[i];
+                q[jj] = fo[jj] + ta * (yh[i] - yt[i]);
+            } else {
+                fo[jj] = T(0);
+                q[jj] = T(-1);
+            }
+        }
+        // the projection of Section 2.3 with the warm-started active-set search of edge_kernel
+        double sp = 0.0, sw = 0.0;
+        int cp = 0, cw = 0;
+#pragma unroll
+        for (int jj = 0; jj < EPT; ++jj) {
+            const double qd = (double)q[jj];
+            if (qd > 0.0) { sp += qd; ++cp; }
+            if (qd > mu0) { sw += qd; ++cw; }
+        }
+        sp = wave_sum(sp); cp = wave_sum(cp);
+        sw = wave_sum(sw); cw = wave_sum(cw);
+        double mu = 0.0;
+        if (sp > cap) {
+            mu = (sp - cap) / cp;
+            int prev = cp;
+            if (cw > 0) {
+                const double mw = (sw - cap) / cw;
+                if (mw > mu) {
+                    mu = mw;
+                    prev = mw >= mu0 ? cw : 0x7fffffff;
+                }
+            }
+            for (int pass = 0; pass <= n; ++pass) {
+                double s = 0.0;
+                int cnt = 0;
+#pragma unroll
+                for (int jj = 0; jj < EPT; ++jj)
+                    if ((double)q[jj] > mu) { s += (double)q[jj]; ++cnt; }
+                s = wave_sum(s);
+                cnt = wave_sum(cnt);
+                if (cnt >= prev) break;
+                mu = (s - cap) / cnt;
+                prev = cnt;
+            }
+        }
+        double gmax = -INFINITY;
+#pragma unroll
+        for (int jj = 0; jj < EPT; ++jj) {
+            const int i = lane + jj * 64;
+            if (i < n) {
+                const double fod = (double)fo[jj];
+                const double fh = fmax((double)q[jj] - mu, 0.0);
+                const double fb = 2.0 * fh - fod;
+                vacc[jj] += out ? -fb : fb;
+                if (CHECK) tacc[jj] += out ? fh : -fh;  // T = -Fhat A^T
+                if (out) {
+                    const T fn = (T)(rho * fh + omr * fod);
+                    Fn[(long long)e * ld + i] = fn;
+                    if (PARTIAL) {
+                        const double d = (double)fn - fod;
+                        dsum += d * d;
+                    }
+                    if (CHECK) {
+                        b.Fhat[(long long)e * ld + i] = (T)fh;
+                        const T dd = (T)(fh - (double)q[jj]);
+                        b.D[(long long)e * ld + i] = dd;
+                        esum += (double)dd * (double)dd;
+                        gmax = fmax(gmax, (double)(yh[i] - yt[i]));
+                    }
+                }
+            }
+        }
+        if (out) {
+            if (lane == 0) mun[e] = mu;
+            if (CHECK) supsum += cap * fmax(wave_max(gmax), 0.0);  // c_l (max_i (Y A)_il)_+
+        }
+    }
+#pragma unroll
+    for (int jj = 0; jj < EPT; ++jj) {
+        vsh[(wv * EPT + jj) * 64 + lane] = vacc[jj];
+        if (CHECK) vsh[4 * EPT * 64 + (wv * EPT + jj) * 64 + lane] = tacc[jj];
+    }
+    __syncthreads();
+    double dy2 = 0.0, p = 0.0, conj = 0.0, rnum = 0.0, rden = 0.0, nonpos = 0.0, yinf = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) {
+        const int jj = i >> 6, L = i & 63;
+        double v = 0.0, t = 0.0;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            v += vsh[(w * EPT + jj) * 64 + L];
+            if (CHECK) t += vsh[4 * EPT * 64 + (w * EPT + jj) * 64 + L];
+        }
+        const long long x = (long long)j * ld + i;
+        const double y = (double)Yc[x];
+        const double w = (double)b.W[x];
+        const double yhat = (i != j) ? prox_dual<UTIL>(y - beta * v, beta, w, g, c.c1) : 0.0;
+        const T yn = (T)(rho * yhat + omr * y);
+        Yn[x] = yn;
+        if (PARTIAL) {
+            const double d = (double)yn - y;
+            dy2 += d * d;
+        }
+        if (CHECK) {
+            b.That[x] = t;
+            double up = 0.0;
+            if (i != j) {
+                if (t > 0.0) {
+                    up = util_du<UTIL>(t, w, g);
+                    p -= util_u<UTIL>(t, w, g);
+                } else {
+                    nonpos += 1.0;
+                }
+                if (y < 0.0) {
+                    conj += util_conj<UTIL>(y, w, g);
+                    const double td = util_traffic<UTIL>(y, w, g) - t;
+                    rnum += td * td;
+                } else {
+                    yinf += 1.0;
+                }
+                rden += t * t;
+            }
+            b.Up[x] = up;
+        }
+    }
+    if (PARTIAL) group_sum<4>(dsum, dy2, red);
+    if (CHECK) {
+        double sup = lane == 0 ? supsum : 0.0;  // supsum is uniform within a wave
+        group_sum<4>(esum, sup, red);
+        supsum = sup;
+        group_sum<4>(p, conj, red);
+        group_sum<4>(rnum, rden, red);
+        group_sum<4>(nonpos, yinf, red);
+    }
+    if (threadIdx.x == 0) {
+        if (PARTIAL) {
+            b.part[pl.dF + j] = dsum;
+            b.part[pl.dY + j] = dy2;
+        }
+        if (CHECK) {
+            b.part[pl.e + j] = esum;
+            b.part[pl.p + j] = p;
+            b.part[pl.conj + j] = conj;
+            b.part[pl.rnum + j] = rnum;
+            b.part[pl.rden + j] = rden;
+            b.part[pl.nonpos + j] = nonpos;
+            b.part[pl.yinf + j] = yinf;
+        }
+    }
+    if (CHECK && threadIdx.x == 0) b.part[pl.sup + j] = supsum;
+}
+
 // ---------------------------------------------------------- residual pass
 // Per edge: G[:,l] = U'[:,head] - U'[:,tail]; partials ||G_l||^2 and <G_l, D_l>.
 // One wave per edge, four edges per 256-thread block.
@@ -502,7 +695,15 @@ constexpr int CTRL_BLOCK = 256;
 __device__ double seg_sum(const double *p, long long len, double *lds)
 {
     double s = 0.0;
-    for (long long x = threadIdx.x; x < len; x += CTRL_BLOCK) s += p[x];
+    long long x = threadIdx.x;
+    for (; x + 7 * CTRL_BLOCK < len; x += 8 * CTRL_BLOCK) {
+        double a[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a[u] = p[x + u * CTRL_BLOCK];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += a[u];
+    }
+    for (; x < len; x += CTRL_BLOCK) s += p[x];
     double z = 0.0;
     group_sum<CTRL_BLOCK / 64>(s, z, lds);
     return s;
@@ -516,20 +717,20 @@ __global__ __launch_bounds__(CTRL_BLOCK) void control_kernel(Consts c, Bufs<T> b
     DevScalars *sc = b.sc;
     if (sc->stop) return;
     const double *P = b.part;
-    const double dF2 = seg_sum(P + pl.dF, c.m, lds);
-    const double dY2 = seg_sum(P + pl.dY, c.nblk_node, lds);
+    const double dF2 = seg_sum(P + pl.dF, c.nep, lds);
+    const double dY2 = seg_sum(P + pl.dY, c.nnp, lds);
     double e = 0, sup = 0, a = 0, bb = 0, psum = 0, conj = 0, rnum = 0, rden = 0, nonpos = 0, yinf = 0;
     if (check) {
-        e = seg_sum(P + pl.e, c.m, lds);
-        sup = seg_sum(P + pl.sup, c.m, lds);
+        e = seg_sum(P + pl.e, c.nep, lds);
+        sup = seg_sum(P + pl.sup, c.nep, lds);
         a = seg_sum(P + pl.a, c.m, lds);
         bb = seg_sum(P + pl.b, c.m, lds);
-        psum = seg_sum(P + pl.p, c.nblk_node, lds);
-        conj = seg_sum(P + pl.conj, c.nblk_node, lds);
-        rnum = seg_sum(P + pl.rnum, c.nblk_node, lds);
-        rden = seg_sum(P + pl.rden, c.nblk_node, lds);
-        nonpos = seg_sum(P + pl.nonpos, c.nblk_node, lds);
-        yinf = seg_sum(P + pl.yinf, c.nblk_node, lds);
+        psum = seg_sum(P + pl.p, c.nnp, lds);
+        conj = seg_sum(P + pl.conj, c.nnp, lds);
+        rnum = seg_sum(P + pl.rnum, c.nnp, lds);
+        rden = seg_sum(P + pl.rden, c.nnp, lds);
+        nonpos = seg_sum(P + pl.nonpos, c.nnp, lds);
+        yinf = seg_sum(P + pl.yinf, c.nnp, lds);
     }
     if (threadIdx.x != 0) return;
     const double dF = sqrt(dF2), dY = sqrt(dY2);
@@ -674,6 +875,36 @@ hipError_t launch_node(const Consts &c, const Bufs<T> &b, const PartLayout &pl, 
     return hipGetLastError();
 }
 
+template <typename T, int EPT, int UTIL>
+static void fused_go(const Consts &c, const Bufs<T> &b, const PartLayout &pl, int parity, bool check, bool partial,
+                     hipStream_t st)
+{
+    if (check)
+        hipLaunchKernelGGL((fused_kernel<T, EPT, UTIL, true, true>), dim3(c.n), dim3(256), 0, st, c, b, pl, parity);
+    else if (partial)
+        hipLaunchKernelGGL((fused_kernel<T, EPT, UTIL, false, true>), dim3(c.n), dim3(256), 0, st, c, b, pl, parity);
+    else
+        hipLaunchKernelGGL((fused_kernel<T, EPT, UTIL, false, false>), dim3(c.n), dim3(256), 0, st, c, b, pl, parity);
+}
+
+template <typename T>
+hipError_t launch_fused(const Consts &c, const Bufs<T> &b, const PartLayout &pl, EdgeShape, int parity, bool check,
+                        bool partial, hipStream_t st)
+{
+#define MCF_FUSED_CASE(E)                                                  \
+    if (c.n <= 64 * E) {                                                   \
+        if (c.utility == 0) fused_go<T, E, 0>(c, b, pl, parity, check, partial, st); \
+        else fused_go<T, E, 1>(c, b, pl, parity, check, partial, st);      \
+        return hipGetLastError();                                          \
+    }
+    MCF_FUSED_CASE(1)
+    MCF_FUSED_CASE(2)
+    MCF_FUSED_CASE(4)
+    MCF_FUSED_CASE(8)
+#undef MCF_FUSED_CASE
+    return hipErrorInvalidValue;
+}
+
 template <typename T>
 hipError_t launch_residual(const Consts &c, const Bufs<T> &b, const PartLayout &pl, EdgeShape, hipStream_t st)
 {
@@ -703,6 +934,8 @@ hipError_t launch_poison(const Bufs<T> &b, int which, long long offset, hipStrea
                                        bool, hipStream_t);                                                      \
     template hipError_t launch_node<T>(const Consts &, const Bufs<T> &, const PartLayout &, bool, bool,          \
                                        hipStream_t);                                                            \
+    template hipError_t launch_fused<T>(const Consts &, const Bufs<T> &, const PartLayout &, EdgeShape, int, bool, \
+                                        bool, hipStream_t);                                                     \
     template hipError_t launch_residual<T>(const Consts &, const Bufs<T> &, const PartLayout &, EdgeShape,       \
                                            hipStream_t);                                                        \
     template hipError_t launch_control<T>(const Consts &, const Bufs<T> &, const PartLayout &, bool, bool,       \

@@ -49,10 +49,13 @@ PartLayout part_layout(int m, int nb)
 
 // Byte offsets of every device buffer inside one allocation.
 struct Plan {
-    size_t F, Fbar, Fhat, D, Y, W, That, Up, cap, mu, tail, head, out_off, in_off, in_edge, part, sc, total;
+    size_t F, Fbar, Fhat, D, Y, W, That, Up, cap, mu, F2, Y2, mu2, tail, head, out_off, in_off, in_edge, part, sc,
+        total;
 };
 
-Plan make_plan(int n, int m, int precision)
+bool use_fused(int n, int mode) { return mode == MCF_KERNELS_FUSED || (mode == MCF_KERNELS_AUTO && n <= FUSED_MAX_N); }
+
+Plan make_plan(int n, int m, int precision, bool fused)
 {
     const size_t es = precision == MCF_FP32 ? 4 : 8;
     const size_t ld = (size_t)padded_ld(n);
@@ -62,7 +65,7 @@ Plan make_plan(int n, int m, int precision)
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes); return at; };
     p.F = take(nm * es);
-    p.Fbar = take(nm * es);
+    p.Fbar = take(fused ? 0 : nm * es);  // the fused iteration never stores Fbar
     p.Fhat = take(nm * es);
     p.D = take(nm * es);
     p.Y = take(nn * es);
@@ -71,6 +74,9 @@ Plan make_plan(int n, int m, int precision)
     p.Up = take(nn * 8);
     p.cap = take((size_t)m * 8);
     p.mu = take((size_t)m * 8);
+    p.F2 = take(fused ? nm * es : 0);  // ping-pong buffers of the fused iteration
+    p.Y2 = take(fused ? nn * es : 0);
+    p.mu2 = take(fused ? (size_t)m * 8 : 0);
     p.tail = take((size_t)m * 4);
     p.head = take((size_t)m * 4);
     p.out_off = take((size_t)(n + 1) * 4);
@@ -100,6 +106,13 @@ struct mcf_solver {
     DevScalars *hs = nullptr;  // pinned host mirror of the device scalars
     int state = MCF_RUNNING;
     long long k = 0;  // PDHG iterations completed (authoritative count)
+    // fused mode: iteration k reads buffer set ((k - anchor_k) & 1) ^ anchor_par
+    long long anchor_k = 0;
+    int anchor_par = 0;
+    int parity(long long kk) const { return c.fused ? (int)((kk - anchor_k) & 1) ^ anchor_par : 0; }
+    // the current state F^{k-1/2}, Y^k lives in buffer set parity(k)
+    size_t cur_F() const { return parity(k) ? plan.F2 : plan.F; }
+    size_t cur_Y() const { return parity(k) ? plan.Y2 : plan.Y; }
     double seconds = 0.0;
     // kernel timing of the edge phase
     bool timing = false;
@@ -127,6 +140,9 @@ struct mcf_solver {
         b.in_edge = (const int *)(base + plan.in_edge);
         b.cap = (const double *)(base + plan.cap);
         b.mu = (double *)(base + plan.mu);
+        b.F2 = (T *)(base + plan.F2);
+        b.Y2 = (T *)(base + plan.Y2);
+        b.mu2 = (double *)(base + plan.mu2);
         b.part = (double *)(base + plan.part);
         b.sc = (DevScalars *)(base + plan.sc);
         return b;
@@ -239,6 +255,8 @@ int do_reset(mcf_solver *s)
     MCF_TRY(hipStreamSynchronize(s->stream));
     s->state = MCF_RUNNING;
     s->k = 0;
+    s->anchor_k = 0;
+    s->anchor_par = 0;
     return MCF_OK;
 }
 
@@ -300,9 +318,14 @@ int enqueue_block(mcf_solver *s, long long count)
             if (!e0 || !e1) return MCF_E_DEVICE;
             MCF_TRY(hipEventRecord(e0, s->stream));
         }
-        MCF_TRY(launch_edge<T>(s->c, b, s->pl, s->sh, check, partial, s->stream));
-        if (s->timing) MCF_TRY(hipEventRecord(e1, s->stream));
-        MCF_TRY(launch_node<T>(s->c, b, s->pl, check, partial, s->stream));
+        if (s->c.fused) {
+            MCF_TRY(launch_fused<T>(s->c, b, s->pl, s->sh, s->parity(k), check, partial, s->stream));
+            if (s->timing) MCF_TRY(hipEventRecord(e1, s->stream));
+        } else {
+            MCF_TRY(launch_edge<T>(s->c, b, s->pl, s->sh, check, partial, s->stream));
+            if (s->timing) MCF_TRY(hipEventRecord(e1, s->stream));
+            MCF_TRY(launch_node<T>(s->c, b, s->pl, check, partial, s->stream));
+        }
         if (check) MCF_TRY(launch_residual<T>(s->c, b, s->pl, s->sh, s->stream));
         if (partial) MCF_TRY(launch_control<T>(s->c, b, s->pl, check, adapt, k + 1, s->stream));
     }
@@ -411,7 +434,7 @@ void mcf_options_default(mcf_options *o)
 size_t mcf_workspace_bytes(int32_t n, int32_t m, int32_t precision)
 {
     if (n < 2 || n > MAX_N || m < 1 || (precision != MCF_FP32 && precision != MCF_FP64)) return 0;
-    return make_plan(n, m, precision).total;
+    return make_plan(n, m, precision, use_fused(n, MCF_KERNELS_AUTO)).total;
 }
 
 const char *mcf_strerror(int code)
@@ -453,6 +476,8 @@ int mcf_create(int32_t n, int32_t m, const int32_t *tail, const int32_t *head, c
     if (o.stop_rule != MCF_STOP_REL_KKT && o.stop_rule != MCF_STOP_PAPER) return MCF_E_ARG;
     if (!(o.rho > 0.0 && o.rho < 2.0) || !(o.omega0 > 0.0) || !(o.theta >= 0.0 && o.theta <= 1.0)) return MCF_E_ARG;
     if (o.check_every < 1) o.check_every = 1;
+    if (o.kernel_mode < MCF_KERNELS_AUTO || o.kernel_mode > MCF_KERNELS_FUSED) return MCF_E_ARG;
+    if (o.kernel_mode == MCF_KERNELS_FUSED && n > FUSED_MAX_N) return MCF_E_ARG;
     for (int l = 0; l < m; ++l) {
         if (tail[l] < 0 || tail[l] >= n || head[l] < 0 || head[l] >= n || tail[l] == head[l]) return MCF_E_ARG;
         if (!(cap[l] > 0.0) || !std::isfinite(cap[l])) return MCF_E_ARG;
@@ -473,7 +498,8 @@ int mcf_create(int32_t n, int32_t m, const int32_t *tail, const int32_t *head, c
     s->opt = o;
     s->ld = padded_ld(n);
     s->sh = edge_shape_for(n);
-    s->plan = make_plan(n, m, o.precision);
+    const bool fused = use_fused(n, o.kernel_mode);
+    s->plan = make_plan(n, m, o.precision, fused);
     s->pl = part_layout(m, node_blocks(n));
     Consts &c = s->c;
     c.n = n;
@@ -490,6 +516,9 @@ int mcf_create(int32_t n, int32_t m, const int32_t *tail, const int32_t *head, c
     c.stop_rule = o.stop_rule;
     c.nblk_node = node_blocks(n);
     c.node_block = node_block_for(n);
+    c.fused = fused ? 1 : 0;
+    c.nep = fused ? n : m;
+    c.nnp = fused ? n : c.nblk_node;
 
     int rc = MCF_OK;
     if (hipSetDevice(o.device) != hipSuccess) rc = MCF_E_DEVICE;
@@ -584,7 +613,7 @@ int mcf_get_solution(mcf_solver *s, double *F, double *T, double *Y)
     int rc = MCF_OK;
     if (F && (rc = download_any(s, s->plan.Fhat, s->m, true, F))) return rc;
     if (T && (rc = download_cols<double>(s, s->plan.That, s->n, false, T))) return rc;
-    if (Y && (rc = download_any(s, s->plan.Y, s->n, false, Y))) return rc;
+    if (Y && (rc = download_any(s, s->cur_Y(), s->n, false, Y))) return rc;
     return MCF_OK;
 }
 
@@ -592,8 +621,8 @@ int mcf_get_state(mcf_solver *s, double *F, double *Y, mcf_scalars *sc)
 {
     if (!s) return MCF_E_ARG;
     int rc = MCF_OK;
-    if (F && (rc = download_any(s, s->plan.F, s->m, true, F))) return rc;
-    if (Y && (rc = download_any(s, s->plan.Y, s->n, false, Y))) return rc;
+    if (F && (rc = download_any(s, s->cur_F(), s->m, true, F))) return rc;
+    if (Y && (rc = download_any(s, s->cur_Y(), s->n, false, Y))) return rc;
     if (sc) {
         if ((rc = pull_scalars(s))) return rc;
         sc->k = s->k;
@@ -606,12 +635,25 @@ int mcf_set_state(mcf_solver *s, const double *F, const double *Y, const mcf_sca
 {
     if (!s || !F) return MCF_E_ARG;
     if (sc && (!(sc->omega > 0.0) || sc->k < 0)) return MCF_E_ARG;
+    // the uploaded state becomes buffer set 0 at iteration k (fused mode)
+    if (s->c.fused && s->parity(s->k) == 1 && !Y) {
+        // keep the current Y: copy it into set 0 first
+        MCF_TRY(hipMemcpyAsync(s->base + s->plan.Y, s->base + s->plan.Y2, (size_t)s->ld * s->n *
+                               (s->precision == MCF_FP32 ? 4 : 8), hipMemcpyDeviceToDevice, s->stream));
+        MCF_TRY(hipMemcpyAsync(s->base + s->plan.mu, s->base + s->plan.mu2, (size_t)s->m * 8,
+                               hipMemcpyDeviceToDevice, s->stream));
+    } else if (s->c.fused && s->parity(s->k) == 1) {
+        MCF_TRY(hipMemcpyAsync(s->base + s->plan.mu, s->base + s->plan.mu2, (size_t)s->m * 8,
+                               hipMemcpyDeviceToDevice, s->stream));
+    }
     int rc = upload_any(s, s->plan.F, s->m, true, F);
     if (!rc && Y) rc = upload_any(s, s->plan.Y, s->n, false, Y);
     if (rc) return rc;
     if ((rc = pull_scalars(s))) return rc;
+    if (sc) s->k = sc->k;
+    s->anchor_k = s->k;
+    s->anchor_par = 0;
     if (sc) {
-        s->k = sc->k;
         s->hs->k = sc->k;
         s->hs->omega = sc->omega;
         s->hs->alpha = s->hs->eta / sc->omega;
@@ -641,8 +683,16 @@ int mcf_debug_poison(mcf_solver *s, int32_t which, int64_t index)
         col = internal;
     }
     const long long off = col * s->ld + i;
-    hipError_t e = s->precision == MCF_FP32 ? launch_poison<float>(s->bufs<float>(), which, off, s->stream)
-                                            : launch_poison<double>(s->bufs<double>(), which, off, s->stream);
+    hipError_t e;
+    if (s->precision == MCF_FP32) {
+        Bufs<float> b = s->bufs<float>();
+        if (s->parity(s->k)) { b.F = b.F2; b.Y = b.Y2; }
+        e = launch_poison<float>(b, which, off, s->stream);
+    } else {
+        Bufs<double> b = s->bufs<double>();
+        if (s->parity(s->k)) { b.F = b.F2; b.Y = b.Y2; }
+        e = launch_poison<double>(b, which, off, s->stream);
+    }
     MCF_TRY(e);
     MCF_TRY(hipStreamSynchronize(s->stream));
     return MCF_OK;
@@ -666,12 +716,13 @@ int mcf_kernel_time(mcf_solver *s, double *edge_ms, int64_t *edge_launches)
     return MCF_OK;
 }
 
-int mcf_layout(const mcf_solver *s, int32_t *ld, int32_t *edge_block, int32_t *edge_ept)
+int mcf_layout(const mcf_solver *s, int32_t *ld, int32_t *edge_block, int32_t *edge_ept, int32_t *kernel_mode)
 {
     if (!s) return MCF_E_ARG;
     if (ld) *ld = (int32_t)s->ld;
     if (edge_block) *edge_block = 64 * s->sh.wpe;
     if (edge_ept) *edge_ept = s->sh.ept;
+    if (kernel_mode) *kernel_mode = s->c.fused ? MCF_KERNELS_FUSED : MCF_KERNELS_TWO_PHASE;
     return MCF_OK;
 }
 

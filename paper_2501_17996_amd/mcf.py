@@ -26,6 +26,7 @@ MCF_FP64, MCF_FP32 = 0, 1
 MCF_STOP_REL_KKT, MCF_STOP_PAPER = 0, 1
 MCF_OK, MCF_E_ARG, MCF_E_GRAPH, MCF_E_NOMEM, MCF_E_DEVICE, MCF_E_STATE = 0, -1, -2, -3, -4, -5
 MCF_RUNNING, MCF_CONVERGED, MCF_MAX_ITER, MCF_DIVERGED = 0, 1, 2, 3
+MCF_KERNELS_AUTO, MCF_KERNELS_TWO_PHASE, MCF_KERNELS_FUSED = 0, 1, 2
 STATE_NAMES = {0: "running", 1: "converged", 2: "max_iter", 3: "diverged"}
 
 EXPORTED = [
@@ -39,7 +40,7 @@ class mcf_options(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int64), ("precision", ctypes.c_int32),
                 ("stop_rule", ctypes.c_int32), ("check_every", ctypes.c_int32), ("k_adapt", ctypes.c_int32),
                 ("rho", ctypes.c_double), ("theta", ctypes.c_double), ("tau", ctypes.c_double),
-                ("omega0", ctypes.c_double), ("device", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("omega0", ctypes.c_double), ("device", ctypes.c_int32), ("kernel_mode", ctypes.c_int32),
                 ("stream", ctypes.c_void_p), ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t)]
 
 
@@ -96,7 +97,7 @@ def lib():
         L.mcf_debug_poison.argtypes = [_vp, ctypes.c_int32, ctypes.c_int64]
         L.mcf_enable_kernel_timing.argtypes = [_vp, ctypes.c_int32]
         L.mcf_kernel_time.argtypes = [_vp, _dp, ctypes.POINTER(ctypes.c_int64)]
-        L.mcf_layout.argtypes = [_vp, _ip, _ip, _ip]
+        L.mcf_layout.argtypes = [_vp, _ip, _ip, _ip, _ip]
         _lib = L
     return _lib
 
@@ -201,9 +202,10 @@ def mcf_kernel_time(h):
 
 
 def mcf_layout(h):
-    ld, b, e = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
-    _check(lib().mcf_layout(h, ctypes.byref(ld), ctypes.byref(b), ctypes.byref(e)), "mcf_layout")
-    return {"ld": ld.value, "edge_block": b.value, "edge_ept": e.value}
+    ld, b, e, km = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().mcf_layout(h, ctypes.byref(ld), ctypes.byref(b), ctypes.byref(e), ctypes.byref(km)), "mcf_layout")
+    return {"ld": ld.value, "edge_block": b.value, "edge_ept": e.value,
+            "kernel_mode": {1: "two_phase", 2: "fused"}.get(km.value, "?")}
 
 
 # --------------------------------------------------------------- convenience
