@@ -38,11 +38,24 @@ def workload(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
-def edge_alg_bytes(n: int, m: int, s: int, check: bool) -> float:
-    """Algorithmic bytes of one edge-phase launch: read F, write F and Fbar
-    (3 s n m) and read every column of Y once (s n^2); a check launch also
-    writes Fhat and D (2 s n m)."""
-    return s * (3.0 * n * m + n * n + (2.0 * n * m if check else 0.0))
+def alg_bytes(n: int, m: int, s: int, fused: bool, check: bool) -> float:
+    """Algorithmic bytes of one launch of the dominant kernel.
+
+    Fused iteration (one launch = one whole PDHG iteration): the per-iteration model
+    s (4 n m + 3 n^2) -- F read and written, Fbar written and read, Y read and written,
+    W read -- even though the fused launch never stores Fbar.
+    Two-phase edge launch: its share of that model, F read, F and Fbar written and each
+    Y column read once, s (3 n m + n^2).
+    A check launch also writes Fhat and D (2 s n m) and, when fused, T and U' (16 n^2)."""
+    if fused:
+        b = s * (4.0 * n * m + 3.0 * n * n)
+        if check:
+            b += 2.0 * s * n * m + 16.0 * n * n
+    else:
+        b = s * (3.0 * n * m + n * n)
+        if check:
+            b += 2.0 * s * n * m
+    return b
 
 
 def cpu_baseline(inst, tol, check_every, budget_s: float):
@@ -71,6 +84,7 @@ def main():
     ap.add_argument("--check-every", type=int, default=10)
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kernel-mode", type=int, default=0, help="0 auto, 1 two-phase, 2 fused")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
@@ -85,7 +99,7 @@ def main():
     s = 4 if prec == mcf.MCF_FP32 else 8
     stream = torch.cuda.current_stream()
     S = mcf.Solver(inst, precision=prec, tol=tol, check_every=args.check_every, max_iter=200000,
-                   stream=stream.cuda_stream)
+                   stream=stream.cuda_stream, kernel_mode=args.kernel_mode)
     for _ in range(args.warmup):
         S.reset()
         S.solve()
@@ -102,8 +116,10 @@ def main():
     edge_ms, launches = mcf.mcf_kernel_time(S.h)
     mcf.mcf_enable_kernel_timing(S.h, False)
     n, m = inst.n, inst.m
-    checks = launches // args.check_every if args.check_every > 0 else 0
-    alg = edge_alg_bytes(n, m, s, False) * (launches - checks) + edge_alg_bytes(n, m, s, True) * checks
+    fused = S.layout()["kernel_mode"] == "fused"
+    # the sampled launches keep the check / regular mix of the whole run
+    checks = launches / args.check_every
+    alg = alg_bytes(n, m, s, fused, False) * (launches - checks) + alg_bytes(n, m, s, fused, True) * checks
     achieved = alg / (edge_ms * 1e-3) / 1e9 if edge_ms > 0 else 0.0
     value = n * m * iters / dt
     out = {
@@ -125,7 +141,8 @@ def main():
                    "time_to_tol_ms": dt / args.steps * 1e3},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "edge phase", "avg_launch_us": edge_ms * 1e3 / max(1, launches),
+                     "kernel": "fused iteration" if fused else "edge phase",
+                     "avg_launch_us": edge_ms * 1e3 / max(1, launches),
                      "launches": launches},
     }
     if not args.no_cpu_baseline:

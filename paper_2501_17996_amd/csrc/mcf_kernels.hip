@@ -477,11 +477,15 @@ __global__ __launch_bounds__(NB) void node_kernel(Consts c, Bufs<T> b, PartLayou
 // Y[:,j].  The tail's workgroup writes the edge's new F column and multiplier.  F, Y and
 // mu are read from one buffer set and written to the other, so no workgroup can see a
 // value of the iteration in flight.
+template <int EPT>
+constexpr int fused_waves() { return EPT <= 4 ? 16 : 8; }
+
 template <typename T, int EPT, int UTIL, bool CHECK, bool PARTIAL>
-__global__ __launch_bounds__(256) void fused_kernel(Consts c, Bufs<T> b, PartLayout pl, int parity)
+__global__ __launch_bounds__(64 * fused_waves<EPT>()) void fused_kernel(Consts c, Bufs<T> b, PartLayout pl, int parity)
 {
-    __shared__ double vsh[(CHECK ? 2 : 1) * 4 * EPT * 64];
-    __shared__ double red[8];
+    constexpr int NWV = fused_waves<EPT>();
+    extern __shared__ double vsh[];  // (CHECK ? 2 : 1) * NWV * EPT * 64 doubles
+    __shared__ double red[2 * NWV];
     if (b.sc->stop) return;
     const int j = blockIdx.x;
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -501,7 +505,7 @@ __global__ __launch_bounds__(256) void fused_kernel(Consts c, Bufs<T> b, PartLay
 #pragma unroll
     for (int jj = 0; jj < EPT; ++jj) vacc[jj] = tacc[jj] = 0.0;
     double dsum = 0.0, esum = 0.0, supsum = 0.0;
-    for (int idx = wv; idx < deg; idx += 4) {
+    for (int idx = wv; idx < deg; idx += NWV) {
         const bool out = idx >= din;
         const int e = out ? o0 + (idx - din) : b.in_edge[i0 + idx];
         const T *yh = Yc + (long long)b.head[e] * ld;
@@ -590,17 +594,17 @@ __global__ __launch_bounds__(256) void fused_kernel(Consts c, Bufs<T> b, PartLay
 #pragma unroll
     for (int jj = 0; jj < EPT; ++jj) {
         vsh[(wv * EPT + jj) * 64 + lane] = vacc[jj];
-        if (CHECK) vsh[4 * EPT * 64 + (wv * EPT + jj) * 64 + lane] = tacc[jj];
+        if (CHECK) vsh[NWV * EPT * 64 + (wv * EPT + jj) * 64 + lane] = tacc[jj];
     }
     __syncthreads();
     double dy2 = 0.0, p = 0.0, conj = 0.0, rnum = 0.0, rden = 0.0, nonpos = 0.0, yinf = 0.0;
-    for (int i = threadIdx.x; i < n; i += 256) {
+    for (int i = threadIdx.x; i < n; i += 64 * NWV) {
         const int jj = i >> 6, L = i & 63;
         double v = 0.0, t = 0.0;
 #pragma unroll
-        for (int w = 0; w < 4; ++w) {
+        for (int w = 0; w < NWV; ++w) {
             v += vsh[(w * EPT + jj) * 64 + L];
-            if (CHECK) t += vsh[4 * EPT * 64 + (w * EPT + jj) * 64 + L];
+            if (CHECK) t += vsh[NWV * EPT * 64 + (w * EPT + jj) * 64 + L];
         }
         const long long x = (long long)j * ld + i;
         const double y = (double)Yc[x];
@@ -634,14 +638,14 @@ __global__ __launch_bounds__(256) void fused_kernel(Consts c, Bufs<T> b, PartLay
             b.Up[x] = up;
         }
     }
-    if (PARTIAL) group_sum<4>(dsum, dy2, red);
+    if (PARTIAL) group_sum<NWV>(dsum, dy2, red);
     if (CHECK) {
         double sup = lane == 0 ? supsum : 0.0;  // supsum is uniform within a wave
-        group_sum<4>(esum, sup, red);
+        group_sum<NWV>(esum, sup, red);
         supsum = sup;
-        group_sum<4>(p, conj, red);
-        group_sum<4>(rnum, rden, red);
-        group_sum<4>(nonpos, yinf, red);
+        group_sum<NWV>(p, conj, red);
+        group_sum<NWV>(rnum, rden, red);
+        group_sum<NWV>(nonpos, yinf, red);
     }
     if (threadIdx.x == 0) {
         if (PARTIAL) {
@@ -691,48 +695,52 @@ __global__ __launch_bounds__(256) void residual_kernel(Consts c, Bufs<T> b, Part
 
 // ----------------------------------------------------------------- control
 constexpr int CTRL_BLOCK = 256;
+constexpr int NQ = 12;  // reduced quantities
 
-__device__ double seg_sum(const double *p, long long len, double *lds)
-{
-    double s = 0.0;
-    long long x = threadIdx.x;
-    for (; x + 7 * CTRL_BLOCK < len; x += 8 * CTRL_BLOCK) {
-        double a[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) a[u] = p[x + u * CTRL_BLOCK];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) s += a[u];
-    }
-    for (; x < len; x += CTRL_BLOCK) s += p[x];
-    double z = 0.0;
-    group_sum<CTRL_BLOCK / 64>(s, z, lds);
-    return s;
-}
-
+// One thread-strided pass over every partial segment with all loads independent, then
+// one block combine: wave sums, and the CTRL_BLOCK/64 wave totals added in wave order.
 template <typename T>
 __global__ __launch_bounds__(CTRL_BLOCK) void control_kernel(Consts c, Bufs<T> b, PartLayout pl, int check,
                                                               int adapt, long long k_after)
 {
-    __shared__ double lds[2 * (CTRL_BLOCK / 64)];
+    constexpr int NW = CTRL_BLOCK / 64;
+    __shared__ double lds[NQ * NW];
     DevScalars *sc = b.sc;
     if (sc->stop) return;
     const double *P = b.part;
-    const double dF2 = seg_sum(P + pl.dF, c.nep, lds);
-    const double dY2 = seg_sum(P + pl.dY, c.nnp, lds);
-    double e = 0, sup = 0, a = 0, bb = 0, psum = 0, conj = 0, rnum = 0, rden = 0, nonpos = 0, yinf = 0;
-    if (check) {
-        e = seg_sum(P + pl.e, c.nep, lds);
-        sup = seg_sum(P + pl.sup, c.nep, lds);
-        a = seg_sum(P + pl.a, c.m, lds);
-        bb = seg_sum(P + pl.b, c.m, lds);
-        psum = seg_sum(P + pl.p, c.nnp, lds);
-        conj = seg_sum(P + pl.conj, c.nnp, lds);
-        rnum = seg_sum(P + pl.rnum, c.nnp, lds);
-        rden = seg_sum(P + pl.rden, c.nnp, lds);
-        nonpos = seg_sum(P + pl.nonpos, c.nnp, lds);
-        yinf = seg_sum(P + pl.yinf, c.nnp, lds);
+    const long long seg[NQ] = {pl.dF, pl.dY, pl.e, pl.sup, pl.a, pl.b, pl.p, pl.conj, pl.rnum, pl.rden, pl.nonpos,
+                               pl.yinf};
+    const long long len[NQ] = {c.nep, c.nnp, c.nep, c.nep, c.m, c.m, c.nnp, c.nnp, c.nnp, c.nnp, c.nnp, c.nnp};
+    const int nq = check ? NQ : 2;
+    double acc[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
+    long long most = 0;
+    for (int q = 0; q < nq; ++q) most = len[q] > most ? len[q] : most;
+    for (long long x = threadIdx.x; x < most; x += CTRL_BLOCK) {
+        double v[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) v[q] = (q < nq && x < len[q]) ? P[seg[q] + x] : 0.0;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) acc[q] += v[q];
     }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const double t = wave_sum(acc[q]);
+        if (lane == 0) lds[q * NW + wid] = t;
+    }
+    __syncthreads();
     if (threadIdx.x != 0) return;
+    double tot[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        double t = 0.0;
+        for (int w = 0; w < NW; ++w) t += lds[q * NW + w];
+        tot[q] = t;
+    }
+    const double dF2 = tot[0], dY2 = tot[1], e = tot[2], sup = tot[3], a = tot[4], bb = tot[5], psum = tot[6],
+                 conj = tot[7], rnum = tot[8], rden = tot[9], nonpos = tot[10], yinf = tot[11];
     const double dF = sqrt(dF2), dY = sqrt(dY2);
     sc->dF = dF;
     sc->dY = dY;
@@ -879,12 +887,15 @@ template <typename T, int EPT, int UTIL>
 static void fused_go(const Consts &c, const Bufs<T> &b, const PartLayout &pl, int parity, bool check, bool partial,
                      hipStream_t st)
 {
+    constexpr int NWV = fused_waves<EPT>();
+    const size_t lds = (check ? 2 : 1) * NWV * EPT * 64 * sizeof(double);
+    const dim3 grid(c.n), block(64 * NWV);
     if (check)
-        hipLaunchKernelGGL((fused_kernel<T, EPT, UTIL, true, true>), dim3(c.n), dim3(256), 0, st, c, b, pl, parity);
+        hipLaunchKernelGGL((fused_kernel<T, EPT, UTIL, true, true>), grid, block, lds, st, c, b, pl, parity);
     else if (partial)
-        hipLaunchKernelGGL((fused_kernel<T, EPT, UTIL, false, true>), dim3(c.n), dim3(256), 0, st, c, b, pl, parity);
+        hipLaunchKernelGGL((fused_kernel<T, EPT, UTIL, false, true>), grid, block, lds, st, c, b, pl, parity);
     else
-        hipLaunchKernelGGL((fused_kernel<T, EPT, UTIL, false, false>), dim3(c.n), dim3(256), 0, st, c, b, pl, parity);
+        hipLaunchKernelGGL((fused_kernel<T, EPT, UTIL, false, false>), grid, block, lds, st, c, b, pl, parity);
 }
 
 template <typename T>
