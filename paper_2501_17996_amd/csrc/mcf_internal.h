@@ -53,6 +53,10 @@ struct Bufs {
     double *mu2;
     double *That, *Up;
     const int *tail, *head, *out_off, *in_off, *in_edge;
+    // per-node incidence list (fused mode): entries inc_off[j] .. inc_off[j+1] are the edges
+    // entering j (in in_edge order) then the edges leaving j, as {edge, other end | 1<<31 if leaving}
+    const int *inc_off;
+    const int2 *inc;
     const double *cap;
     double *mu;            // per-edge multiplier of the last projection (warm start of the next one)
     double *part;

@@ -477,13 +477,15 @@ __global__ __launch_bounds__(NB) void node_kernel(Consts c, Bufs<T> b, PartLayou
 // Y[:,j].  The tail's workgroup writes the edge's new F column and multiplier.  F, Y and
 // mu are read from one buffer set and written to the other, so no workgroup can see a
 // value of the iteration in flight.
-template <int EPT>
-constexpr int fused_waves() { return EPT <= 4 ? 16 : 8; }
+template <int EPT, bool CHECK>
+constexpr int fused_waves() { return (CHECK || EPT > 4) ? 8 : 16; }
 
 template <typename T, int EPT, int UTIL, bool CHECK, bool PARTIAL>
-__global__ __launch_bounds__(64 * fused_waves<EPT>()) void fused_kernel(Consts c, Bufs<T> b, PartLayout pl, int parity)
+__global__ __launch_bounds__((64 * fused_waves<EPT, CHECK>())) void fused_kernel(Consts c, Bufs<T> b, PartLayout pl,
+                                                                               int parity)
 {
-    constexpr int NWV = fused_waves<EPT>();
+    constexpr int NWV = fused_waves<EPT, CHECK>();
+    constexpr int RPT = (64 * EPT + 64 * NWV - 1) / (64 * NWV);  // node-phase rows per thread
     extern __shared__ double vsh[];  // (CHECK ? 2 : 1) * NWV * EPT * 64 doubles
     __shared__ double red[2 * NWV];
     if (b.sc->stop) return;
@@ -499,17 +501,32 @@ __global__ __launch_bounds__(64 * fused_waves<EPT>()) void fused_kernel(Consts c
     double *mun = parity ? b.mu : b.mu2;
     const T ta = (T)b.sc->alpha;
     const double beta = b.sc->beta, g = c.gamma, rho = c.rho, omr = 1.0 - c.rho;
-    const int i0 = b.in_off[j], din = b.in_off[j + 1] - i0;
-    const int o0 = b.out_off[j], deg = din + (b.out_off[j + 1] - o0);
+    const int k0 = b.inc_off[j], deg = b.inc_off[j + 1] - k0;
+    const T *yj = Yc + (long long)j * ld;
+    // node-phase operands, loaded before the edge loop so their latency overlaps it
+    double yrow[RPT], wrow[RPT];
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+        const int i = threadIdx.x + r * 64 * NWV;
+        yrow[r] = i < n ? (double)yj[i] : 0.0;
+        wrow[r] = i < n ? (double)b.W[(long long)j * ld + i] : 0.0;
+    }
+    // column j of Y, shared by every edge incident to j (its head or its tail column)
+    T yjl[EPT];
+#pragma unroll
+    for (int jj = 0; jj < EPT; ++jj) {
+        const int i = lane + jj * 64;
+        yjl[jj] = i < n ? yj[i] : T(0);
+    }
     double vacc[EPT], tacc[EPT];
 #pragma unroll
     for (int jj = 0; jj < EPT; ++jj) vacc[jj] = tacc[jj] = 0.0;
     double dsum = 0.0, esum = 0.0, supsum = 0.0;
     for (int idx = wv; idx < deg; idx += NWV) {
-        const bool out = idx >= din;
-        const int e = out ? o0 + (idx - din) : b.in_edge[i0 + idx];
-        const T *yh = Yc + (long long)b.head[e] * ld;
-        const T *yt = Yc + (long long)b.tail[e] * ld;
+        const int2 ent = b.inc[k0 + idx];
+        const bool out = ent.y < 0;  // edge leaves j: j is its tail
+        const int e = ent.x, o = ent.y & 0x7fffffff;
+        const T *yo = Yc + (long long)o * ld;
         const T *f = Fc + (long long)e * ld;
         const double cap = b.cap[e], mu0 = muc[e];
         T fo[EPT], q[EPT];
@@ -518,7 +535,8 @@ __global__ __launch_bounds__(64 * fused_waves<EPT>()) void fused_kernel(Consts c
             const int i = lane + jj * 64;
             if (i < n) {
                 fo[jj] = f[i];
-                q[jj] = fo[jj] + ta * (yh[i] - yt[i]);
+                const T yv = yo[i];
+                q[jj] = fo[jj] + ta * (out ? yv - yjl[jj] : yjl[jj] - yv);  // Y[:,head] - Y[:,tail]
             } else {
                 fo[jj] = T(0);
                 q[jj] = T(-1);
@@ -581,7 +599,7 @@ __global__ __launch_bounds__(64 * fused_waves<EPT>()) void fused_kernel(Consts c
                         const T dd = (T)(fh - (double)q[jj]);
                         b.D[(long long)e * ld + i] = dd;
                         esum += (double)dd * (double)dd;
-                        gmax = fmax(gmax, (double)(yh[i] - yt[i]));
+                        gmax = fmax(gmax, (double)(yo[i] - yjl[jj]));  // (Y A)_il of the leaving edge
                     }
                 }
             }
@@ -598,7 +616,10 @@ __global__ __launch_bounds__(64 * fused_waves<EPT>()) void fused_kernel(Consts c
     }
     __syncthreads();
     double dy2 = 0.0, p = 0.0, conj = 0.0, rnum = 0.0, rden = 0.0, nonpos = 0.0, yinf = 0.0;
-    for (int i = threadIdx.x; i < n; i += 64 * NWV) {
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+        const int i = threadIdx.x + r * 64 * NWV;
+        if (i >= n) continue;
         const int jj = i >> 6, L = i & 63;
         double v = 0.0, t = 0.0;
 #pragma unroll
@@ -607,8 +628,7 @@ __global__ __launch_bounds__(64 * fused_waves<EPT>()) void fused_kernel(Consts c
             if (CHECK) t += vsh[NWV * EPT * 64 + (w * EPT + jj) * 64 + L];
         }
         const long long x = (long long)j * ld + i;
-        const double y = (double)Yc[x];
-        const double w = (double)b.W[x];
+        const double y = yrow[r], w = wrow[r];
         const double yhat = (i != j) ? prox_dual<UTIL>(y - beta * v, beta, w, g, c.c1) : 0.0;
         const T yn = (T)(rho * yhat + omr * y);
         Yn[x] = yn;
@@ -654,6 +674,7 @@ __global__ __launch_bounds__(64 * fused_waves<EPT>()) void fused_kernel(Consts c
         }
         if (CHECK) {
             b.part[pl.e + j] = esum;
+            b.part[pl.sup + j] = supsum;
             b.part[pl.p + j] = p;
             b.part[pl.conj + j] = conj;
             b.part[pl.rnum + j] = rnum;
@@ -662,7 +683,6 @@ __global__ __launch_bounds__(64 * fused_waves<EPT>()) void fused_kernel(Consts c
             b.part[pl.yinf + j] = yinf;
         }
     }
-    if (CHECK && threadIdx.x == 0) b.part[pl.sup + j] = supsum;
 }
 
 // ---------------------------------------------------------- residual pass
@@ -887,15 +907,17 @@ template <typename T, int EPT, int UTIL>
 static void fused_go(const Consts &c, const Bufs<T> &b, const PartLayout &pl, int parity, bool check, bool partial,
                      hipStream_t st)
 {
-    constexpr int NWV = fused_waves<EPT>();
-    const size_t lds = (check ? 2 : 1) * NWV * EPT * 64 * sizeof(double);
-    const dim3 grid(c.n), block(64 * NWV);
+    constexpr int NWC = fused_waves<EPT, true>(), NWR = fused_waves<EPT, false>();
+    const dim3 grid(c.n);
     if (check)
-        hipLaunchKernelGGL((fused_kernel<T, EPT, UTIL, true, true>), grid, block, lds, st, c, b, pl, parity);
+        hipLaunchKernelGGL((fused_kernel<T, EPT, UTIL, true, true>), grid, dim3(64 * NWC),
+                           2 * NWC * EPT * 64 * sizeof(double), st, c, b, pl, parity);
     else if (partial)
-        hipLaunchKernelGGL((fused_kernel<T, EPT, UTIL, false, true>), grid, block, lds, st, c, b, pl, parity);
+        hipLaunchKernelGGL((fused_kernel<T, EPT, UTIL, false, true>), grid, dim3(64 * NWR),
+                           NWR * EPT * 64 * sizeof(double), st, c, b, pl, parity);
     else
-        hipLaunchKernelGGL((fused_kernel<T, EPT, UTIL, false, false>), grid, block, lds, st, c, b, pl, parity);
+        hipLaunchKernelGGL((fused_kernel<T, EPT, UTIL, false, false>), grid, dim3(64 * NWR),
+                           NWR * EPT * 64 * sizeof(double), st, c, b, pl, parity);
 }
 
 template <typename T>

@@ -4,6 +4,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <deque>
 #include <new>
 #include <vector>
 
@@ -52,8 +53,8 @@ PartLayout part_layout(int m, int nb)
 
 // Byte offsets of every device buffer inside one allocation.
 struct Plan {
-    size_t F, Fbar, Fhat, D, Y, W, That, Up, cap, mu, F2, Y2, mu2, tail, head, out_off, in_off, in_edge, part, sc,
-        total;
+    size_t F, Fbar, Fhat, D, Y, W, That, Up, cap, mu, F2, Y2, mu2, tail, head, out_off, in_off, in_edge, inc_off,
+        inc, part, sc, total;
 };
 
 bool use_fused(int n, int mode) { return mode == MCF_KERNELS_FUSED || (mode == MCF_KERNELS_AUTO && n <= FUSED_MAX_N); }
@@ -85,6 +86,8 @@ Plan make_plan(int n, int m, int precision, bool fused)
     p.out_off = take((size_t)(n + 1) * 4);
     p.in_off = take((size_t)(n + 1) * 4);
     p.in_edge = take((size_t)m * 4);
+    p.inc_off = take(fused ? (size_t)(n + 1) * 4 : 0);
+    p.inc = take(fused ? (size_t)m * 2 * 8 : 0);
     p.part = take((size_t)pl.total * 8);
     p.sc = take(sizeof(DevScalars));
     p.total = o;
@@ -106,7 +109,8 @@ struct mcf_solver {
     bool own_mem = false;
     hipStream_t stream = nullptr;
     bool own_stream = false;
-    DevScalars *hs = nullptr;  // pinned host mirror of the device scalars
+    DevScalars *hs = nullptr;  // pinned host mirror of the device scalars; hs[1], hs[2] are block snapshots
+    hipEvent_t blk_ev[2] = {nullptr, nullptr};  // completion of the snapshot copies
     int state = MCF_RUNNING;
     long long k = 0;  // PDHG iterations completed (authoritative count)
     // fused mode: iteration k reads buffer set ((k - anchor_k) & 1) ^ anchor_par
@@ -119,8 +123,8 @@ struct mcf_solver {
     double seconds = 0.0;
     // kernel timing of the edge phase
     bool timing = false;
-    std::vector<hipEvent_t> ev;  // pairs (start, stop) of the current block
-    size_t ev_used = 0;
+    std::vector<hipEvent_t> ev;  // pairs (start, stop) recorded during the current drive
+    size_t ev_used = 0, ev_done = 0;
     double edge_ms = 0.0;
     long long edge_launches = 0;
 
@@ -141,6 +145,8 @@ struct mcf_solver {
         b.out_off = (const int *)(base + plan.out_off);
         b.in_off = (const int *)(base + plan.in_off);
         b.in_edge = (const int *)(base + plan.in_edge);
+        b.inc_off = (const int *)(base + plan.inc_off);
+        b.inc = (const int2 *)(base + plan.inc);
         b.cap = (const double *)(base + plan.cap);
         b.mu = (double *)(base + plan.mu);
         b.F2 = (T *)(base + plan.F2);
@@ -241,6 +247,20 @@ int upload_problem(mcf_solver *s, const int *tail, const int *head, const double
     MCF_TRY(hipMemcpyAsync(b + p.out_off, out_off.data(), (n + 1) * 4, hipMemcpyHostToDevice, st));
     MCF_TRY(hipMemcpyAsync(b + p.in_off, in_off.data(), (n + 1) * 4, hipMemcpyHostToDevice, st));
     MCF_TRY(hipMemcpyAsync(b + p.in_edge, in_edge.data(), m * 4, hipMemcpyHostToDevice, st));
+    // per-node incidence list of the fused iteration: entering edges, then leaving edges
+    std::vector<int> inc_off(n + 1, 0);
+    std::vector<int2> inc((size_t)2 * m);
+    if (s->c.fused) {
+        size_t at = 0;
+        for (int j = 0; j < n; ++j) {
+            inc_off[j] = (int)at;
+            for (int k = in_off[j]; k < in_off[j + 1]; ++k) inc[at++] = make_int2(in_edge[k], t[in_edge[k]]);
+            for (int e = out_off[j]; e < out_off[j + 1]; ++e) inc[at++] = make_int2(e, (int)(h[e] | 0x80000000u));
+        }
+        inc_off[n] = (int)at;
+        MCF_TRY(hipMemcpyAsync(b + p.inc_off, inc_off.data(), (n + 1) * 4, hipMemcpyHostToDevice, st));
+        MCF_TRY(hipMemcpyAsync(b + p.inc, inc.data(), inc.size() * sizeof(int2), hipMemcpyHostToDevice, st));
+    }
     MCF_TRY(hipMemsetAsync(b + p.part, 0, (size_t)s->pl.total * 8, st));
     std::memset(s->hs, 0, sizeof(DevScalars));
     s->hs->eta = eta;
@@ -289,28 +309,29 @@ hipEvent_t next_event(mcf_solver *s)
     return s->ev[s->ev_used++];
 }
 
-int collect_events(mcf_solver *s)
+// Adds up the bracketed launches whose events lie in [s->ev_done, upto).
+int collect_events(mcf_solver *s, size_t upto)
 {
-    for (size_t k = 0; k + 1 < s->ev_used; k += 2) {
+    for (size_t k = s->ev_done; k + 1 < upto; k += 2) {
         float ms = 0.f;
         MCF_TRY(hipEventElapsedTime(&ms, s->ev[k], s->ev[k + 1]));
         s->edge_ms += ms;
         s->edge_launches += 1;
     }
-    s->ev_used = 0;
+    s->ev_done = upto;
     return MCF_OK;
 }
 
-// Enqueues `count` iterations starting at iteration s->k; only the last one is a check
+// Enqueues `count` iterations starting at iteration k0; only the last one is a check
 // iteration.  Iterations that adapt omega (k a multiple of k_adapt) or check the residual
 // write step-norm partials and end in a control launch; the others are two launches.
 template <typename T>
-int enqueue_block(mcf_solver *s, long long count)
+int enqueue_block(mcf_solver *s, long long k0, long long count)
 {
     const Bufs<T> b = s->bufs<T>();
     const int ka = s->opt.k_adapt;
     for (long long it = 0; it < count; ++it) {
-        const long long k = s->k + it;
+        const long long k = k0 + it;
         const bool check = it == count - 1;
         const bool adapt = ka > 0 && k % ka == 0;
         const bool partial = check || adapt;
@@ -336,11 +357,18 @@ int enqueue_block(mcf_solver *s, long long count)
     return MCF_OK;
 }
 
-// The iteration driver.  With stop_test the device raises `stop` when the stop rule
-// holds at a check; the host polls the scalars after every block of check_every
-// iterations.  Without it, exactly target - k iterations run (divergence still stops).
+// The iteration driver.  Blocks of check_every iterations end with an asynchronous copy
+// of the device scalars into a pinned snapshot slot; two blocks are kept in flight, so the
+// device never waits for the host to read a snapshot.  With stop_test the device raises
+// `stop` when the stop rule holds at a check, and every launch queued after that returns at
+// entry.  Without it, exactly target - k iterations run (divergence still stops).
 int drive(mcf_solver *s, long long target, bool stop_test)
 {
+    struct Pending {
+        long long k0, count;
+        int slot;
+        size_t ev_end;
+    };
     auto t0 = std::chrono::steady_clock::now();
     int rc = pull_scalars(s);
     if (rc) return rc;
@@ -350,23 +378,42 @@ int drive(mcf_solver *s, long long target, bool stop_test)
         if ((rc = push_scalars(s))) return rc;
     }
     const long long K = std::max(1, s->opt.check_every);
-    for (;;) {
+    std::deque<Pending> pend;
+    long long k_next = s->k;
+    int slot = 0;
+    s->ev_used = s->ev_done = 0;
+    bool stopped = s->hs->stop != 0;
+    while (!stopped) {
+        while (pend.size() < 2 && k_next < target) {
+            const long long count = std::min(K, target - k_next);
+            rc = s->precision == MCF_FP32 ? enqueue_block<float>(s, k_next, count)
+                                          : enqueue_block<double>(s, k_next, count);
+            if (rc) return rc;
+            MCF_TRY(hipMemcpyAsync(s->hs + 1 + slot, s->dsc(), sizeof(DevScalars), hipMemcpyDeviceToHost,
+                                   s->stream));
+            MCF_TRY(hipEventRecord(s->blk_ev[slot], s->stream));
+            pend.push_back({k_next, count, slot, s->ev_used});
+            slot ^= 1;
+            k_next += count;
+        }
+        if (pend.empty()) break;
+        const Pending r = pend.front();
+        pend.pop_front();
+        MCF_TRY(hipEventSynchronize(s->blk_ev[r.slot]));
+        *s->hs = s->hs[1 + r.slot];
+        if (s->timing && (rc = collect_events(s, r.ev_end))) return rc;
         if (s->hs->stop) {
-            s->state = s->hs->state == MCF_DIVERGED ? MCF_DIVERGED : MCF_CONVERGED;
-            break;
+            s->k = s->hs->k;  // the launches after the stop did nothing
+            stopped = true;
+        } else {
+            s->k = r.k0 + r.count;
         }
-        if (s->k >= target) {
-            s->state = stop_test ? MCF_MAX_ITER : MCF_RUNNING;
-            break;
-        }
-        const long long count = std::min(K, target - s->k);
-        rc = s->precision == MCF_FP32 ? enqueue_block<float>(s, count) : enqueue_block<double>(s, count);
-        if (rc) return rc;
-        if ((rc = pull_scalars(s))) return rc;
-        // a stop raised inside the block skipped the launches after it
-        s->k = s->hs->stop ? s->hs->k : s->k + count;
-        if (s->timing && (rc = collect_events(s))) return rc;
     }
+    MCF_TRY(hipStreamSynchronize(s->stream));  // drain a block queued behind a stop
+    if (stopped) s->state = s->hs->state == MCF_DIVERGED ? MCF_DIVERGED : MCF_CONVERGED;
+    else s->state = stop_test ? MCF_MAX_ITER : MCF_RUNNING;
+    if (s->timing && (rc = collect_events(s, s->ev_used))) return rc;
+    s->ev_used = s->ev_done = 0;
     s->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return MCF_OK;
 }
@@ -459,6 +506,8 @@ void mcf_destroy(mcf_solver *s)
     if (!s) return;
     if (s->stream) (void)hipStreamSynchronize(s->stream);
     for (hipEvent_t e : s->ev) (void)hipEventDestroy(e);
+    for (hipEvent_t e : s->blk_ev)
+        if (e) (void)hipEventDestroy(e);
     if (s->own_mem && s->base) (void)hipFree(s->base);
     if (s->hs) (void)hipHostFree(s->hs);
     if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
@@ -535,8 +584,10 @@ int mcf_create(int32_t n, int32_t m, const int32_t *tail, const int32_t *head, c
             rc = MCF_E_DEVICE;
         }
     }
-    if (!rc && hipHostMalloc((void **)&s->hs, sizeof(DevScalars), hipHostMallocDefault) != hipSuccess)
+    if (!rc && hipHostMalloc((void **)&s->hs, 3 * sizeof(DevScalars), hipHostMallocDefault) != hipSuccess)
         rc = MCF_E_NOMEM;
+    for (int q = 0; q < 2 && !rc; ++q)
+        if (hipEventCreateWithFlags(&s->blk_ev[q], hipEventDisableTiming) != hipSuccess) rc = MCF_E_DEVICE;
     if (!rc) {
         if (o.workspace) {
             if (o.workspace_bytes < s->plan.total || ((uintptr_t)o.workspace % ALIGN)) rc = MCF_E_ARG;
@@ -706,7 +757,7 @@ int mcf_enable_kernel_timing(mcf_solver *s, int32_t enable)
 {
     if (!s) return MCF_E_ARG;
     s->timing = enable != 0;
-    s->ev_used = 0;
+    s->ev_used = s->ev_done = 0;
     s->edge_ms = 0.0;
     s->edge_launches = 0;
     return MCF_OK;
