@@ -63,12 +63,13 @@ struct Bufs {
     DevScalars *sc;
 };
 
-// Per-edge launch shape: `wpe` waves (of 64 lanes) per edge column, `ept` entries per lane.
-// With wpe == 1 a 256-thread block carries 4 edges, one per wave.
+// Per-edge launch shape of the two-phase edge kernel: `wpe` waves (of 64 lanes) per edge
+// column and `ept` 16-byte vectors per lane.  With wpe == 1 a 256-thread block carries 4
+// edges, one per wave.
 struct EdgeShape {
     int wpe, ept;
 };
-EdgeShape edge_shape_for(int n);
+EdgeShape edge_shape_for(int n, int bytes);
 
 // Kernel launchers (defined in mcf_kernels.hip).
 template <typename T>

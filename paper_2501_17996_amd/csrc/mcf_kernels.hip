@@ -213,6 +213,21 @@ __device__ __forceinline__ double prox_dual(double y, double beta, double w, dou
     return -t;
 }
 
+// ------------------------------------------------------------- XCD mapping
+// Workgroups are dealt round-robin to the 8 XCDs (each with its own L2).  Mapping launch
+// index b to work item (b % 8) * per + b / 8 gives every XCD one contiguous range of work
+// items, so neighbours in the work order (edges with the same tail) share an L2.  The grid
+// has 8 * per workgroups; those mapped past `items` return at once.
+constexpr int NUM_XCD = 8;
+
+__device__ __forceinline__ int xcd_item(int b, int items)
+{
+    const int per = (items + NUM_XCD - 1) / NUM_XCD;
+    return (b % NUM_XCD) * per + b / NUM_XCD;
+}
+
+inline int xcd_grid(int items) { return ((items + NUM_XCD - 1) / NUM_XCD) * NUM_XCD; }
+
 // ------------------------------------------------------------------- init
 template <typename T>
 __global__ void init_kernel(Consts c, Bufs<T> b, double omega0)
@@ -250,7 +265,36 @@ __global__ void init_kernel(Consts c, Bufs<T> b, double omega0)
 }
 
 // -------------------------------------------------------------- edge phase
-// WPE waves per edge column, each lane keeping EPT entries of F[:,l] and q in registers.
+// 16-byte vectors of the iterate type: 4 floats or 2 doubles.
+template <typename T> struct Vec;
+template <> struct Vec<float> { using type = float4; static constexpr int N = 4; };
+template <> struct Vec<double> { using type = double2; static constexpr int N = 2; };
+
+template <typename T>
+__device__ __forceinline__ void vload(const T *p, T (&x)[Vec<T>::N])
+{
+    const typename Vec<T>::type v = *reinterpret_cast<const typename Vec<T>::type *>(p);
+    if constexpr (Vec<T>::N == 4) { x[0] = v.x; x[1] = v.y; x[2] = v.z; x[3] = v.w; }
+    else { x[0] = v.x; x[1] = v.y; }
+}
+
+template <typename T>
+__device__ __forceinline__ void vstore(T *p, const T (&x)[Vec<T>::N])
+{
+    typename Vec<T>::type v;
+    if constexpr (Vec<T>::N == 4) { v.x = x[0]; v.y = x[1]; v.z = x[2]; v.w = x[3]; }
+    else { v.x = x[0]; v.y = x[1]; }
+    *reinterpret_cast<typename Vec<T>::type *>(p) = v;
+}
+
+// The largest value of type T that is <= x: for q of type T, q > x exactly when q > below(x).
+__device__ __forceinline__ float below(double x, float) { return __double2float_rd(x); }
+__device__ __forceinline__ double below(double x, double) { return x; }
+
+// WPE waves per edge column (WPE == 1: a 256-thread block carries 4 edges, one per wave),
+// each lane holding NV 16-byte vectors of F[:,l] and q.  Vector v of lane t covers entries
+// (v * 64 * WPE + t) * VEC .. + VEC - 1; a vector that starts below n is loaded whole: the
+// padding rows n .. ld-1 of F and Y are zero, so their q is 0 and they never enter a support.
 // mu (Section 2.3, Section 2.6): mu = 0 if sum (q)_+ <= c; otherwise the support S and
 // mu = (sum_S q - c)/|S| satisfy S = {q > mu}.  Any mu' with S' = {q > mu'} nonempty
 // gives the lower bound (sum_{S'} q - c)/|S'| <= mu (the linear function it zeroes lies
@@ -259,13 +303,17 @@ __global__ void init_kernel(Consts c, Bufs<T> b, double omega0)
 // stops exactly when |S| stops shrinking.  The search starts from the larger of the
 // bounds given by S' = {q > 0} and S' = {q > mu of the previous iteration}, so a
 // column whose support did not move needs two block sums instead of five or six.
-template <typename T, int WPE, int EPT, bool CHECK, bool PARTIAL>
+template <typename T, int WPE, int NV, bool CHECK, bool PARTIAL>
 __global__ __launch_bounds__(WPE == 1 ? 256 : 64 * WPE) void edge_kernel(Consts c, Bufs<T> b, PartLayout pl)
 {
+    constexpr int VEC = Vec<T>::N;
     constexpr int LANES = 64 * WPE;  // threads per edge column
     __shared__ double lds[2 * WPE];
     if (b.sc->stop) return;
-    const int e = WPE == 1 ? (int)blockIdx.x * 4 + (int)(threadIdx.x >> 6) : (int)blockIdx.x;
+    const int items = WPE == 1 ? (c.m + 3) / 4 : c.m;
+    const int blk = xcd_item(blockIdx.x, items);
+    if (blk >= items) return;
+    const int e = WPE == 1 ? blk * 4 + (int)(threadIdx.x >> 6) : blk;
     if (e >= c.m) return;  // whole waves only (WPE == 1): no block barrier follows
     const int t = WPE == 1 ? (int)(threadIdx.x & 63) : (int)threadIdx.x;
     const int n = c.n;
@@ -276,32 +324,49 @@ __global__ __launch_bounds__(WPE == 1 ? 256 : 64 * WPE) void edge_kernel(Consts 
     T *f = b.F + (long long)e * ld;
     const double cap = b.cap[e];
     const double mu0 = b.mu[e];
-    T fo[EPT], q[EPT];
+    T fo[NV][VEC], q[NV][VEC];
 #pragma unroll
-    for (int j = 0; j < EPT; ++j) {
-        const int i = t + j * LANES;
+    for (int v = 0; v < NV; ++v) {
+        const int i = (v * LANES + t) * VEC;
         if (i < n) {
-            fo[j] = f[i];
-            q[j] = fo[j] + ta * (yh[i] - yt[i]);
+            T a[VEC], bh[VEC], bt[VEC];
+            vload(f + i, a);
+            vload(yh + i, bh);
+            vload(yt + i, bt);
+#pragma unroll
+            for (int u = 0; u < VEC; ++u) {
+                fo[v][u] = a[u];
+                q[v][u] = a[u] + ta * (bh[u] - bt[u]);
+            }
         } else {
-            fo[j] = T(0);
-            q[j] = T(-1);  // never in the support
+#pragma unroll
+            for (int u = 0; u < VEC; ++u) {
+                fo[v][u] = T(0);
+                q[v][u] = T(0);
+            }
         }
     }
+    // Sums over a support {q > thr}: each 16-byte vector is first added in the iterate type
+    // (in a fixed order), then in FP64.  Converting per vector rather than per entry keeps the
+    // compiler from holding an FP64 copy of every q across the passes.
+    auto support_sum = [&](T thr, double &s, int &cnt) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            T part = T(0);
+#pragma unroll
+            for (int u = 0; u < VEC; ++u)
+                if (q[v][u] > thr) {
+                    part += q[v][u];
+                    ++cnt;
+                }
+            s += (double)part;
+        }
+    };
+    const T thr0 = below(mu0, T(0));
     double sp = 0.0, sw = 0.0;
     int cp = 0, cw = 0;
-#pragma unroll
-    for (int j = 0; j < EPT; ++j) {
-        const double qd = (double)q[j];
-        if (qd > 0.0) {
-            sp += qd;
-            ++cp;
-        }
-        if (qd > mu0) {
-            sw += qd;
-            ++cw;
-        }
-    }
+    support_sum(T(0), sp, cp);
+    support_sum(thr0, sw, cw);
     group_sum<WPE>(sp, cp, lds);
     group_sum<WPE>(sw, cw, lds);
     double mu = 0.0;
@@ -318,12 +383,7 @@ __global__ __launch_bounds__(WPE == 1 ? 256 : 64 * WPE) void edge_kernel(Consts 
         for (int pass = 0; pass <= n; ++pass) {
             double s = 0.0;
             int cnt = 0;
-#pragma unroll
-            for (int j = 0; j < EPT; ++j)
-                if ((double)q[j] > mu) {
-                    s += (double)q[j];
-                    ++cnt;
-                }
+            support_sum(below(mu, T(0)), s, cnt);
             group_sum<WPE>(s, cnt, lds);
             if (cnt >= prev) break;
             mu = (s - cap) / cnt;
@@ -334,24 +394,37 @@ __global__ __launch_bounds__(WPE == 1 ? 256 : 64 * WPE) void edge_kernel(Consts 
     const double rho = c.rho, omr = 1.0 - c.rho;
     double dsum = 0.0, esum = 0.0, gmax = -INFINITY;
 #pragma unroll
-    for (int j = 0; j < EPT; ++j) {
-        const int i = t + j * LANES;
+    for (int v = 0; v < NV; ++v) {
+        const int i = (v * LANES + t) * VEC;
         if (i < n) {
-            const double fod = (double)fo[j];
-            const double fh = fmax((double)q[j] - mu, 0.0);
-            const T fn = (T)(rho * fh + omr * fod);
-            f[i] = fn;
-            fb[i] = (T)(2.0 * fh - fod);
-            if (PARTIAL) {
-                const double d = (double)fn - fod;
-                dsum += d * d;
+            T fn[VEC], fbv[VEC], fhv[VEC], dv[VEC];
+#pragma unroll
+            for (int u = 0; u < VEC; ++u) {
+                const double fod = (double)fo[v][u];
+                const double fh = fmax((double)q[v][u] - mu, 0.0);
+                fn[u] = (T)(rho * fh + omr * fod);
+                fbv[u] = (T)(2.0 * fh - fod);
+                if (PARTIAL) {
+                    const double d = (double)fn[u] - fod;
+                    dsum += d * d;
+                }
+                if (CHECK) {
+                    fhv[u] = (T)fh;
+                    dv[u] = (T)(fh - (double)q[v][u]);
+                    esum += (double)dv[u] * (double)dv[u];
+                }
             }
+            vstore(f + i, fn);
+            vstore(fb + i, fbv);
             if (CHECK) {
-                b.Fhat[(long long)e * ld + i] = (T)fh;
-                const T dd = (T)(fh - (double)q[j]);
-                b.D[(long long)e * ld + i] = dd;
-                esum += (double)dd * (double)dd;
-                gmax = fmax(gmax, (double)(yh[i] - yt[i]));
+                vstore(b.Fhat + (long long)e * ld + i, fhv);
+                vstore(b.D + (long long)e * ld + i, dv);
+                T bh[VEC], bt[VEC];
+                vload(yh + i, bh);
+                vload(yt + i, bt);
+#pragma unroll
+                for (int u = 0; u < VEC; ++u)
+                    if (i + u < n) gmax = fmax(gmax, (double)(bh[u] - bt[u]));
             }
         }
     }
@@ -692,7 +765,10 @@ template <typename T>
 __global__ __launch_bounds__(256) void residual_kernel(Consts c, Bufs<T> b, PartLayout pl)
 {
     if (b.sc->stop) return;
-    const int e = (int)blockIdx.x * 4 + (int)(threadIdx.x >> 6);
+    const int items = (c.m + 3) / 4;
+    const int blk = xcd_item(blockIdx.x, items);
+    if (blk >= items) return;
+    const int e = blk * 4 + (int)(threadIdx.x >> 6);
     if (e >= c.m) return;
     const int lane = threadIdx.x & 63;
     const long long ld = c.ld;
@@ -826,17 +902,20 @@ __global__ void poison_kernel(Bufs<T> b, int which, long long off)
 }
 
 // ---------------------------------------------------------------- launchers
-EdgeShape edge_shape_for(int n)
+// Waves per edge column and 16-byte vectors per lane for an n-row column of an iterate of
+// `bytes`-byte entries: enough lanes to cover n, with a 256-thread block (four waves) for
+// large n so that several blocks stay resident on a CU, and 512 threads for the largest
+// FP64 columns to keep the per-lane register count bounded.
+EdgeShape edge_shape_for(int n, int bytes)
 {
-    if (n <= 64) return {1, 1};
-    if (n <= 128) return {1, 2};
-    if (n <= 256) return {1, 4};
-    if (n <= 512) return {2, 4};
-    if (n <= 1024) return {4, 4};
-    if (n <= 2048) return {4, 8};
-    if (n <= 4096) return {8, 8};
-    if (n <= 8192) return {8, 16};
-    return {8, 32};
+    const int vec = 16 / bytes;
+    if (n <= 64 * vec) return {1, 1};
+    if (n <= 128 * vec) return {1, 2};
+    const int nvs[] = {1, 2, 4, 8, 12, 16};
+    for (int nv : nvs)
+        if (n <= 256 * vec * nv && (bytes == 4 || nv <= 8)) return {4, nv};
+    if (n <= 512 * vec * 8) return {8, 8};
+    return {8, 16};
 }
 
 int node_block_for(int n) { return n <= 512 ? 64 : 256; }
@@ -848,34 +927,38 @@ hipError_t launch_init(const Consts &c, const Bufs<T> &b, double omega0, hipStre
     return hipGetLastError();
 }
 
-template <typename T, int WPE, int EPT>
+template <typename T, int WPE, int NV>
 static void edge_go(const Consts &c, const Bufs<T> &b, const PartLayout &pl, bool check, bool partial,
                     hipStream_t st)
 {
-    const dim3 grid(WPE == 1 ? (c.m + 3) / 4 : c.m), block(WPE == 1 ? 256 : 64 * WPE);
+    const dim3 grid(xcd_grid(WPE == 1 ? (c.m + 3) / 4 : c.m)), block(WPE == 1 ? 256 : 64 * WPE);
     if (check)
-        hipLaunchKernelGGL((edge_kernel<T, WPE, EPT, true, true>), grid, block, 0, st, c, b, pl);
+        hipLaunchKernelGGL((edge_kernel<T, WPE, NV, true, true>), grid, block, 0, st, c, b, pl);
     else if (partial)
-        hipLaunchKernelGGL((edge_kernel<T, WPE, EPT, false, true>), grid, block, 0, st, c, b, pl);
+        hipLaunchKernelGGL((edge_kernel<T, WPE, NV, false, true>), grid, block, 0, st, c, b, pl);
     else
-        hipLaunchKernelGGL((edge_kernel<T, WPE, EPT, false, false>), grid, block, 0, st, c, b, pl);
+        hipLaunchKernelGGL((edge_kernel<T, WPE, NV, false, false>), grid, block, 0, st, c, b, pl);
 }
 
 template <typename T>
 hipError_t launch_edge(const Consts &c, const Bufs<T> &b, const PartLayout &pl, EdgeShape sh, bool check,
                        bool partial, hipStream_t st)
 {
-#define MCF_EDGE_CASE(W, E) \
-    if (sh.wpe == W && sh.ept == E) { edge_go<T, W, E>(c, b, pl, check, partial, st); return hipGetLastError(); }
+#define MCF_EDGE_CASE(W, V) \
+    if (sh.wpe == W && sh.ept == V) { edge_go<T, W, V>(c, b, pl, check, partial, st); return hipGetLastError(); }
     MCF_EDGE_CASE(1, 1)
     MCF_EDGE_CASE(1, 2)
-    MCF_EDGE_CASE(1, 4)
-    MCF_EDGE_CASE(2, 4)
+    MCF_EDGE_CASE(4, 1)
+    MCF_EDGE_CASE(4, 2)
     MCF_EDGE_CASE(4, 4)
     MCF_EDGE_CASE(4, 8)
-    MCF_EDGE_CASE(8, 8)
-    MCF_EDGE_CASE(8, 16)
-    MCF_EDGE_CASE(8, 32)
+    if constexpr (sizeof(T) == 4) {
+        MCF_EDGE_CASE(4, 12)
+        MCF_EDGE_CASE(4, 16)
+    } else {
+        MCF_EDGE_CASE(8, 8)
+        MCF_EDGE_CASE(8, 16)
+    }
 #undef MCF_EDGE_CASE
     return hipErrorInvalidValue;
 }
@@ -941,7 +1024,7 @@ hipError_t launch_fused(const Consts &c, const Bufs<T> &b, const PartLayout &pl,
 template <typename T>
 hipError_t launch_residual(const Consts &c, const Bufs<T> &b, const PartLayout &pl, EdgeShape, hipStream_t st)
 {
-    hipLaunchKernelGGL(residual_kernel<T>, dim3((c.m + 3) / 4), dim3(256), 0, st, c, b, pl);
+    hipLaunchKernelGGL(residual_kernel<T>, dim3(xcd_grid((c.m + 3) / 4)), dim3(256), 0, st, c, b, pl);
     return hipGetLastError();
 }
 

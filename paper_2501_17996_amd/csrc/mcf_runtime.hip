@@ -550,7 +550,7 @@ int mcf_create(int32_t n, int32_t m, const int32_t *tail, const int32_t *head, c
     s->precision = o.precision;
     s->opt = o;
     s->ld = padded_ld(n);
-    s->sh = edge_shape_for(n);
+    s->sh = edge_shape_for(n, o.precision == MCF_FP32 ? 4 : 8);
     const bool fused = use_fused(n, o.kernel_mode);
     s->plan = make_plan(n, m, o.precision, fused);
     s->pl = part_layout(m, node_blocks(n));
@@ -776,7 +776,7 @@ int mcf_layout(const mcf_solver *s, int32_t *ld, int32_t *edge_block, int32_t *e
     if (!s) return MCF_E_ARG;
     if (ld) *ld = (int32_t)s->ld;
     if (edge_block) *edge_block = 64 * s->sh.wpe;
-    if (edge_ept) *edge_ept = s->sh.ept;
+    if (edge_ept) *edge_ept = s->sh.ept * (s->precision == MCF_FP32 ? 4 : 2);
     if (kernel_mode) *kernel_mode = s->c.fused ? MCF_KERNELS_FUSED : MCF_KERNELS_TWO_PHASE;
     return MCF_OK;
 }
