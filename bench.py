@@ -81,10 +81,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
-    ap.add_argument("--check-every", type=int, default=10)
+    ap.add_argument("--check-every", type=int, default=20)
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-mode", type=int, default=0, help="0 auto, 1 two-phase, 2 fused")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one 256 MiB device copy first (a counter reference of known size)")
     ap.add_argument("--iters", type=int, default=0,
                     help="run this many iterations per step instead of a full solve (large workloads)")
     args = ap.parse_args()
@@ -102,6 +104,13 @@ def main():
     stream = torch.cuda.current_stream()
     S = mcf.Solver(inst, precision=prec, tol=tol, check_every=args.check_every, max_iter=200000,
                    stream=stream.cuda_stream, kernel_mode=args.kernel_mode)
+    if args.copy_calibration:
+        src = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
     def step():
         S.reset()
         return S.run(args.iters) if args.iters > 0 else S.solve()
