@@ -24,6 +24,20 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
+def measured_traffic(workload: str):
+    """HBM bytes per launch of the dominant kernel from the committed counter runs, or None
+    when the kernel source changed after the counters were taken."""
+    import hashlib
+    try:
+        rec = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))
+        src = open(os.path.join(ROOT, "paper_2501_17996_amd", "csrc", "mcf_kernels.hip"), "rb").read()
+    except OSError:
+        return None
+    if hashlib.sha256(src).hexdigest() != rec.get("kernels_sha256") or workload not in rec:
+        return None
+    return rec[workload]["bytes_per_launch"]
+
+
 def workload(name: str):
     from paper_2501_17996_amd import instances as I
     if name == "c2":
@@ -154,7 +168,9 @@ def main():
                    "step": f"{args.iters} iterations from the cold start" if args.iters > 0 else "full solve",
                    "time_to_tol_ms": dt / args.steps * 1e3},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(args.workload) if args.kernel_mode == 0 else None,
+                     "alg_bytes_per_launch": alg / max(1, launches),
                      "kernel": "fused iteration" if fused else "edge phase",
                      "avg_launch_us": edge_ms * 1e3 / max(1, launches),
                      "launches": launches},
