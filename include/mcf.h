@@ -157,6 +157,54 @@ int mcf_kernel_time(mcf_solver *s, double *edge_ms, int64_t *edge_launches);
  * entries per thread, and the kernel organisation in use (MCF_KERNELS_TWO_PHASE or _FUSED). */
 int mcf_layout(const mcf_solver *s, int32_t *ld, int32_t *edge_block, int32_t *edge_ept, int32_t *kernel_mode);
 
+/* ---------------------------------------------------------------- batching pool
+ * A pool runs many instances (each created with n <= 512 and the pool's precision) in one
+ * stream: every pool iteration is one launch that performs one PDHG iteration of every active
+ * instance, whatever its size or utility, followed on check iterations by one residual and one
+ * control launch for all of them.  Each instance follows its own Algorithm 2.1 (its own
+ * iteration count, primal weight, adapt schedule and stop test); the residual of every
+ * instance is evaluated at the last iteration of each mcf_pool_step.  Instances are admitted
+ * and retired between steps (continuous batching); a converged instance stops iterating at
+ * once and its slot can be reused after mcf_pool_retire.
+ * Usage: create solvers (optionally inside caller workspaces), admit them, then repeat
+ * { mcf_pool_step; host work; mcf_pool_sync; poll; retire; admit }.  While admitted, a solver
+ * answers only mcf_status (the record of the last sync); its other calls return MCF_E_STATE. */
+typedef struct mcf_pool mcf_pool;
+enum { MCF_POOL_MAX_SLOTS = 256 };
+
+/* Creates a pool on `device`.  precision: MCF_FP32 or MCF_FP64 for every instance admitted;
+ * hbm_budget: largest sum of mcf_workspace_bytes of the admitted instances (0: no limit);
+ * max_slots: 1 .. MCF_POOL_MAX_SLOTS; check_every: default step length for callers;
+ * stream: hipStream_t or NULL for a stream owned by the pool. */
+int mcf_pool_create(int32_t device, int32_t precision, size_t hbm_budget, int32_t max_slots, int32_t check_every,
+                    void *stream, mcf_pool **out);
+
+/* Admits a solver into a free slot.  MCF_E_NOMEM when no slot is free or the budget would be
+ * exceeded (retry after a retire); MCF_E_ARG when the solver is already pooled, has another
+ * precision, or uses the two-phase iteration (n > 512); MCF_E_STATE when it has converged or
+ * diverged.  The solver keeps its state and continues from its current iteration. */
+int mcf_pool_admit(mcf_pool *p, mcf_solver *s, int32_t *slot);
+
+/* Enqueues `iters` pool iterations (the last one checks every instance) and returns without
+ * waiting.  Waits first for a step still in flight. */
+int mcf_pool_step(mcf_pool *p, int32_t iters);
+
+/* Waits for the step in flight and refreshes every slot's record. */
+int mcf_pool_sync(mcf_pool *p);
+
+/* The record of the instance in `slot`, as of the last sync. */
+int mcf_pool_poll(mcf_pool *p, int32_t slot, mcf_result *out);
+
+/* Releases a slot (after waiting for the step in flight).  The solver becomes a standalone
+ * handle again, at the state it reached in the pool. */
+int mcf_pool_retire(mcf_pool *p, int32_t slot);
+
+/* Number of occupied slots, workspace bytes admitted, pool iterations run so far. */
+int mcf_pool_info(const mcf_pool *p, int32_t *active, size_t *used_bytes, int64_t *iterations);
+
+/* Retires every slot and releases the pool.  NULL-safe. */
+void mcf_pool_destroy(mcf_pool *p);
+
 #ifdef __cplusplus
 }
 #endif

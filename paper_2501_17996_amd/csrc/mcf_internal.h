@@ -96,4 +96,24 @@ hipError_t launch_poison(const Bufs<T> &b, int which, long long offset, hipStrea
 
 int node_block_for(int n);
 
+// One slot of a batching pool: the instance and the values recorded when it was admitted.
+// At pool iteration G the slot performs its iteration k = k0 + (G - G0), reading buffer set
+// par0 ^ ((G - G0) & 1), until its stop flag is raised or k reaches max_iter.
+template <typename T>
+struct SlotDesc {
+    Consts c;
+    Bufs<T> b;
+    PartLayout pl;
+    long long G0, k0, max_iter;
+    int par0, active;
+};
+
+constexpr int POOL_WAVES = 8;  // waves per node workgroup in the batched iteration
+
+template <typename T>
+hipError_t launch_pool_iteration(const SlotDesc<T> *slots, const int2 *work, int nwork, int nslots, int max_m,
+                                 int max_ept, long long G, bool check, bool control, hipStream_t st);
+template <typename T>
+hipError_t launch_pool_gather(const SlotDesc<T> *slots, int nslots, DevScalars *out, hipStream_t st);
+
 }  // namespace mcf

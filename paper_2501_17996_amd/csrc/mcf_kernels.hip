@@ -553,16 +553,13 @@ __global__ __launch_bounds__(NB) void node_kernel(Consts c, Bufs<T> b, PartLayou
 template <int EPT, bool CHECK>
 constexpr int fused_waves() { return (CHECK || EPT > 4) ? 8 : 16; }
 
-template <typename T, int EPT, int UTIL, bool CHECK, bool PARTIAL>
-__global__ __launch_bounds__((64 * fused_waves<EPT, CHECK>())) void fused_kernel(Consts c, Bufs<T> b, PartLayout pl,
-                                                                               int parity)
+// The body of one fused iteration for node j, run by NWV waves.  `vsh` holds
+// (CHECK ? 2 : 1) * NWV * EPT * 64 doubles and `red` 2 * NWV doubles of LDS.
+template <typename T, int EPT, int UTIL, bool CHECK, bool PARTIAL, int NWV>
+__device__ __forceinline__ void fused_body(const Consts &c, const Bufs<T> &b, const PartLayout &pl, int parity, int j,
+                                           double *vsh, double *red)
 {
-    constexpr int NWV = fused_waves<EPT, CHECK>();
     constexpr int RPT = (64 * EPT + 64 * NWV - 1) / (64 * NWV);  // node-phase rows per thread
-    extern __shared__ double vsh[];  // (CHECK ? 2 : 1) * NWV * EPT * 64 doubles
-    __shared__ double red[2 * NWV];
-    if (b.sc->stop) return;
-    const int j = blockIdx.x;
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int n = c.n;
     const long long ld = c.ld;
@@ -758,18 +755,23 @@ __global__ __launch_bounds__((64 * fused_waves<EPT, CHECK>())) void fused_kernel
     }
 }
 
+template <typename T, int EPT, int UTIL, bool CHECK, bool PARTIAL>
+__global__ __launch_bounds__((64 * fused_waves<EPT, CHECK>())) void fused_kernel(Consts c, Bufs<T> b, PartLayout pl,
+                                                                               int parity)
+{
+    constexpr int NWV = fused_waves<EPT, CHECK>();
+    extern __shared__ double vsh[];
+    __shared__ double red[2 * NWV];
+    if (b.sc->stop) return;
+    fused_body<T, EPT, UTIL, CHECK, PARTIAL, NWV>(c, b, pl, parity, (int)blockIdx.x, vsh, red);
+}
+
 // ---------------------------------------------------------- residual pass
 // Per edge: G[:,l] = U'[:,head] - U'[:,tail]; partials ||G_l||^2 and <G_l, D_l>.
 // One wave per edge, four edges per 256-thread block.
 template <typename T>
-__global__ __launch_bounds__(256) void residual_kernel(Consts c, Bufs<T> b, PartLayout pl)
+__device__ __forceinline__ void residual_body(const Consts &c, const Bufs<T> &b, const PartLayout &pl, int e)
 {
-    if (b.sc->stop) return;
-    const int items = (c.m + 3) / 4;
-    const int blk = xcd_item(blockIdx.x, items);
-    if (blk >= items) return;
-    const int e = blk * 4 + (int)(threadIdx.x >> 6);
-    if (e >= c.m) return;
     const int lane = threadIdx.x & 63;
     const long long ld = c.ld;
     const double *uh = b.Up + (long long)b.head[e] * ld;
@@ -789,20 +791,31 @@ __global__ __launch_bounds__(256) void residual_kernel(Consts c, Bufs<T> b, Part
     }
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void residual_kernel(Consts c, Bufs<T> b, PartLayout pl)
+{
+    if (b.sc->stop) return;
+    const int items = (c.m + 3) / 4;
+    const int blk = xcd_item(blockIdx.x, items);
+    if (blk >= items) return;
+    const int e = blk * 4 + (int)(threadIdx.x >> 6);
+    if (e >= c.m) return;
+    residual_body<T>(c, b, pl, e);
+}
+
 // ----------------------------------------------------------------- control
 constexpr int CTRL_BLOCK = 256;
 constexpr int NQ = 12;  // reduced quantities
 
 // One thread-strided pass over every partial segment with all loads independent, then
 // one block combine: wave sums, and the CTRL_BLOCK/64 wave totals added in wave order.
+// Run by one CTRL_BLOCK-thread block; `lds` holds NQ * CTRL_BLOCK/64 doubles.
 template <typename T>
-__global__ __launch_bounds__(CTRL_BLOCK) void control_kernel(Consts c, Bufs<T> b, PartLayout pl, int check,
-                                                              int adapt, long long k_after)
+__device__ __forceinline__ void control_body(const Consts &c, const Bufs<T> &b, const PartLayout &pl, int check,
+                                             int adapt, long long k_after, double *lds)
 {
     constexpr int NW = CTRL_BLOCK / 64;
-    __shared__ double lds[NQ * NW];
     DevScalars *sc = b.sc;
-    if (sc->stop) return;
     const double *P = b.part;
     const long long seg[NQ] = {pl.dF, pl.dY, pl.e, pl.sup, pl.a, pl.b, pl.p, pl.conj, pl.rnum, pl.rden, pl.nonpos,
                                pl.yinf};
@@ -895,10 +908,103 @@ __global__ __launch_bounds__(CTRL_BLOCK) void control_kernel(Consts c, Bufs<T> b
 }
 
 template <typename T>
+__global__ __launch_bounds__(CTRL_BLOCK) void control_kernel(Consts c, Bufs<T> b, PartLayout pl, int check,
+                                                              int adapt, long long k_after)
+{
+    __shared__ double lds[NQ * (CTRL_BLOCK / 64)];
+    if (b.sc->stop) return;
+    control_body<T>(c, b, pl, check, adapt, k_after, lds);
+}
+
+template <typename T>
 __global__ void poison_kernel(Bufs<T> b, int which, long long off)
 {
     if (which == 0) b.F[off] = (T)NAN;
     else b.Y[off] = (T)NAN;
+}
+
+// ------------------------------------------------------------------- pool
+// Batched iteration of many instances (each with n <= FUSED_MAX_N): one launch per
+// iteration covers every node of every active slot.  A slot's iteration count, buffer
+// parity and adapt schedule follow from the pool's iteration counter G and the values
+// recorded at admission, so nothing per slot is written by the host between launches.
+template <typename T>
+__device__ __forceinline__ bool slot_live(const SlotDesc<T> &d, long long G, long long &k)
+{
+    if (!d.active || d.b.sc->stop) return false;
+    k = d.k0 + (G - d.G0);
+    return k < d.max_iter;
+}
+
+// CHECK is uniform over a launch (every slot checks at the same pool iteration), so the
+// check variant is a kernel of its own and the register count of the regular kernel stays low.
+template <typename T, int EPT, int UTIL, bool CHECK>
+__device__ __forceinline__ void pool_body(const SlotDesc<T> &d, int parity, int j, bool partial, double *vsh,
+                                          double *red)
+{
+    if (CHECK) fused_body<T, EPT, UTIL, true, true, POOL_WAVES>(d.c, d.b, d.pl, parity, j, vsh, red);
+    else if (partial) fused_body<T, EPT, UTIL, false, true, POOL_WAVES>(d.c, d.b, d.pl, parity, j, vsh, red);
+    else fused_body<T, EPT, UTIL, false, false, POOL_WAVES>(d.c, d.b, d.pl, parity, j, vsh, red);
+}
+
+template <typename T, int EPT, bool CHECK>
+__device__ __forceinline__ void pool_util(const SlotDesc<T> &d, int parity, int j, bool partial, double *vsh,
+                                          double *red)
+{
+    if (d.c.utility == 0) pool_body<T, EPT, 0, CHECK>(d, parity, j, partial, vsh, red);
+    else pool_body<T, EPT, 1, CHECK>(d, parity, j, partial, vsh, red);
+}
+
+template <typename T, bool CHECK>
+__global__ __launch_bounds__(64 * POOL_WAVES) void pool_fused_kernel(const SlotDesc<T> *slots, const int2 *work,
+                                                                     long long G)
+{
+    extern __shared__ double vsh[];
+    __shared__ double red[2 * POOL_WAVES];
+    const int2 wk = work[blockIdx.x];
+    const SlotDesc<T> &d = slots[wk.x];
+    long long k;
+    if (!slot_live(d, G, k)) return;
+    const int parity = d.par0 ^ (int)((G - d.G0) & 1);
+    const bool partial = CHECK || (d.c.k_adapt > 0 && k % d.c.k_adapt == 0);
+    const int n = d.c.n;
+    if (n <= 64) pool_util<T, 1, CHECK>(d, parity, wk.y, partial, vsh, red);
+    else if (n <= 128) pool_util<T, 2, CHECK>(d, parity, wk.y, partial, vsh, red);
+    else if (n <= 256) pool_util<T, 4, CHECK>(d, parity, wk.y, partial, vsh, red);
+    else pool_util<T, 8, CHECK>(d, parity, wk.y, partial, vsh, red);
+}
+
+// grid (ceil(max m / 4), slots): one wave per edge of a slot
+template <typename T>
+__global__ __launch_bounds__(256) void pool_residual_kernel(const SlotDesc<T> *slots, long long G)
+{
+    const SlotDesc<T> &d = slots[blockIdx.y];
+    long long k;
+    if (!slot_live(d, G, k)) return;
+    const int e = (int)blockIdx.x * 4 + (int)(threadIdx.x >> 6);
+    if (e >= d.c.m) return;
+    residual_body<T>(d.c, d.b, d.pl, e);
+}
+
+// one block per slot; acts on the slots whose iteration G adapted omega or was checked
+template <typename T>
+__global__ __launch_bounds__(CTRL_BLOCK) void pool_control_kernel(const SlotDesc<T> *slots, long long G, int check)
+{
+    __shared__ double lds[NQ * (CTRL_BLOCK / 64)];
+    const SlotDesc<T> &d = slots[blockIdx.x];
+    long long k;
+    if (!slot_live(d, G, k)) return;
+    const bool adapt = d.c.k_adapt > 0 && k % d.c.k_adapt == 0;
+    if (!check && !adapt) return;
+    control_body<T>(d.c, d.b, d.pl, check, adapt, k + 1, lds);
+}
+
+// copies every slot's scalar record into one array (one host copy per block of iterations)
+template <typename T>
+__global__ void pool_gather_kernel(const SlotDesc<T> *slots, int nslots, DevScalars *out)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < nslots && slots[s].active) out[s] = *slots[s].b.sc;
 }
 
 // ---------------------------------------------------------------- launchers
@@ -1044,6 +1150,29 @@ hipError_t launch_poison(const Bufs<T> &b, int which, long long offset, hipStrea
     return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_pool_iteration(const SlotDesc<T> *slots, const int2 *work, int nwork, int nslots, int max_m,
+                                 int max_ept, long long G, bool check, bool control, hipStream_t st)
+{
+    const size_t lds = (check ? 2 : 1) * POOL_WAVES * max_ept * 64 * sizeof(double);
+    if (check)
+        hipLaunchKernelGGL((pool_fused_kernel<T, true>), dim3(nwork), dim3(64 * POOL_WAVES), lds, st, slots, work, G);
+    else
+        hipLaunchKernelGGL((pool_fused_kernel<T, false>), dim3(nwork), dim3(64 * POOL_WAVES), lds, st, slots, work, G);
+    if (check)
+        hipLaunchKernelGGL(pool_residual_kernel<T>, dim3((max_m + 3) / 4, nslots), dim3(256), 0, st, slots, G);
+    if (control)
+        hipLaunchKernelGGL(pool_control_kernel<T>, dim3(nslots), dim3(CTRL_BLOCK), 0, st, slots, G, check ? 1 : 0);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_pool_gather(const SlotDesc<T> *slots, int nslots, DevScalars *out, hipStream_t st)
+{
+    hipLaunchKernelGGL(pool_gather_kernel<T>, dim3((nslots + 63) / 64), dim3(64), 0, st, slots, nslots, out);
+    return hipGetLastError();
+}
+
 #define MCF_INSTANTIATE(T)                                                                                      \
     template hipError_t launch_init<T>(const Consts &, const Bufs<T> &, double, hipStream_t);                   \
     template hipError_t launch_edge<T>(const Consts &, const Bufs<T> &, const PartLayout &, EdgeShape, bool,     \
@@ -1056,7 +1185,10 @@ hipError_t launch_poison(const Bufs<T> &b, int which, long long offset, hipStrea
                                            hipStream_t);                                                        \
     template hipError_t launch_control<T>(const Consts &, const Bufs<T> &, const PartLayout &, bool, bool,       \
                                           long long, hipStream_t);                                              \
-    template hipError_t launch_poison<T>(const Bufs<T> &, int, long long, hipStream_t);
+    template hipError_t launch_poison<T>(const Bufs<T> &, int, long long, hipStream_t);                      \
+    template hipError_t launch_pool_iteration<T>(const SlotDesc<T> *, const int2 *, int, int, int, int, long long, \
+                                                 bool, bool, hipStream_t);                                    \
+    template hipError_t launch_pool_gather<T>(const SlotDesc<T> *, int, DevScalars *, hipStream_t);
 
 MCF_INSTANTIATE(float)
 MCF_INSTANTIATE(double)

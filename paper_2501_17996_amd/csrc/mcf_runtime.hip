@@ -98,6 +98,8 @@ Plan make_plan(int n, int m, int precision, bool fused)
 
 struct mcf_solver {
     int n = 0, m = 0, precision = 0;
+    mcf_pool *pool = nullptr;  // set while the instance is admitted to a batching pool
+    int pool_slot = -1;
     long long ld = 0;
     mcf_options opt{};
     Consts c{};
@@ -504,6 +506,7 @@ const char *mcf_strerror(int code)
 void mcf_destroy(mcf_solver *s)
 {
     if (!s) return;
+    if (s->pool) mcf_pool_retire(s->pool, s->pool_slot);
     if (s->stream) (void)hipStreamSynchronize(s->stream);
     for (hipEvent_t e : s->ev) (void)hipEventDestroy(e);
     for (hipEvent_t e : s->blk_ev)
@@ -614,18 +617,21 @@ int mcf_create(int32_t n, int32_t m, const int32_t *tail, const int32_t *head, c
 int mcf_reset(mcf_solver *s)
 {
     if (!s) return MCF_E_ARG;
+    if (s->pool) return MCF_E_STATE;
     return reset_any(s);
 }
 
 int mcf_solve(mcf_solver *s)
 {
     if (!s) return MCF_E_ARG;
+    if (s->pool) return MCF_E_STATE;
     return drive(s, s->opt.max_iter, true);
 }
 
 int mcf_run(mcf_solver *s, int64_t iters)
 {
     if (!s || iters < 0) return MCF_E_ARG;
+    if (s->pool) return MCF_E_STATE;
     int rc = pull_scalars(s);
     if (rc) return rc;
     if (s->hs->state == MCF_CONVERGED) {  // run on past a met stop rule
@@ -665,6 +671,7 @@ int mcf_status(const mcf_solver *s, mcf_result *r)
 int mcf_get_solution(mcf_solver *s, double *F, double *T, double *Y)
 {
     if (!s) return MCF_E_ARG;
+    if (s->pool) return MCF_E_STATE;
     int rc = MCF_OK;
     if (F && (rc = download_any(s, s->plan.Fhat, s->m, true, F))) return rc;
     if (T && (rc = download_cols<double>(s, s->plan.That, s->n, false, T))) return rc;
@@ -675,6 +682,7 @@ int mcf_get_solution(mcf_solver *s, double *F, double *T, double *Y)
 int mcf_get_state(mcf_solver *s, double *F, double *Y, mcf_scalars *sc)
 {
     if (!s) return MCF_E_ARG;
+    if (s->pool) return MCF_E_STATE;
     int rc = MCF_OK;
     if (F && (rc = download_any(s, s->cur_F(), s->m, true, F))) return rc;
     if (Y && (rc = download_any(s, s->cur_Y(), s->n, false, Y))) return rc;
@@ -689,6 +697,7 @@ int mcf_get_state(mcf_solver *s, double *F, double *Y, mcf_scalars *sc)
 int mcf_set_state(mcf_solver *s, const double *F, const double *Y, const mcf_scalars *sc)
 {
     if (!s || !F) return MCF_E_ARG;
+    if (s->pool) return MCF_E_STATE;
     if (sc && (!(sc->omega > 0.0) || sc->k < 0)) return MCF_E_ARG;
     // the uploaded state becomes buffer set 0 at iteration k (fused mode)
     if (s->c.fused && s->parity(s->k) == 1 && !Y) {
@@ -726,6 +735,7 @@ int mcf_set_state(mcf_solver *s, const double *F, const double *Y, const mcf_sca
 int mcf_debug_poison(mcf_solver *s, int32_t which, int64_t index)
 {
     if (!s || (which != 0 && which != 1)) return MCF_E_ARG;
+    if (s->pool) return MCF_E_STATE;
     const int n = s->n;
     const long long cols = which == 0 ? s->m : n;
     if (index < 0 || index >= cols * n) return MCF_E_ARG;
@@ -781,4 +791,254 @@ int mcf_layout(const mcf_solver *s, int32_t *ld, int32_t *edge_block, int32_t *e
     return MCF_OK;
 }
 
+
+// ================================================================ batching pool
+}  // extern "C"
+
+struct mcf_pool {
+    int device = 0, precision = 0, max_slots = 0, check_every = 1;
+    size_t budget = 0, used = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    long long G = 0;  // pool iterations enqueued so far
+    std::vector<mcf_solver *> slot;
+    std::vector<SlotDesc<double>> desc;  // host copy (the layout does not depend on the iterate type)
+    SlotDesc<double> *d_desc = nullptr;
+    int2 *d_work = nullptr;
+    DevScalars *d_snap = nullptr;
+    DevScalars *h_snap = nullptr;         // pinned
+    SlotDesc<double> *h_desc = nullptr;   // pinned staging
+    int2 *h_work = nullptr;               // pinned staging
+    int nwork = 0, max_m = 1, max_ept = 1;
+    hipEvent_t done = nullptr;
+    bool pending = false;
+};
+
+namespace {
+
+int pool_upload(mcf_pool *p)
+{
+    // the stream is idle here (callers synchronize first), so the staging buffers are free
+    std::memcpy(p->h_desc, p->desc.data(), sizeof(SlotDesc<double>) * p->max_slots);
+    MCF_TRY(hipMemcpyAsync(p->d_desc, p->h_desc, sizeof(SlotDesc<double>) * p->max_slots, hipMemcpyHostToDevice,
+                           p->stream));
+    int nw = 0, max_m = 1, max_n = 1;
+    for (int sl = 0; sl < p->max_slots; ++sl) {
+        if (!p->desc[sl].active) continue;
+        const int n = p->desc[sl].c.n;
+        for (int j = 0; j < n; ++j) p->h_work[nw++] = make_int2(sl, j);
+        max_m = std::max(max_m, p->desc[sl].c.m);
+        max_n = std::max(max_n, n);
+    }
+    p->nwork = nw;
+    p->max_m = max_m;
+    p->max_ept = max_n <= 64 ? 1 : max_n <= 128 ? 2 : max_n <= 256 ? 4 : 8;
+    if (nw) MCF_TRY(hipMemcpyAsync(p->d_work, p->h_work, sizeof(int2) * nw, hipMemcpyHostToDevice, p->stream));
+    MCF_TRY(hipStreamSynchronize(p->stream));
+    return MCF_OK;
+}
+
+// iteration count and state of a slot from the latest snapshot
+void pool_refresh(mcf_pool *p, int sl)
+{
+    mcf_solver *s = p->slot[sl];
+    const SlotDesc<double> &d = p->desc[sl];
+    *s->hs = p->h_snap[sl];
+    long long k = std::min(d.k0 + (p->G - d.G0), (long long)d.max_iter);
+    if (s->hs->stop) k = s->hs->k;
+    s->k = k;
+    s->anchor_k = k;
+    s->anchor_par = d.par0 ^ (int)((k - d.k0) & 1);
+    if (s->hs->stop) s->state = s->hs->state == MCF_DIVERGED ? MCF_DIVERGED : MCF_CONVERGED;
+    else if (k >= d.max_iter) s->state = MCF_MAX_ITER;
+    else s->state = MCF_RUNNING;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mcf_pool_create(int32_t device, int32_t precision, size_t hbm_budget, int32_t max_slots, int32_t check_every,
+                    void *stream, mcf_pool **out)
+{
+    if (!out) return MCF_E_ARG;
+    *out = nullptr;
+    if ((precision != MCF_FP32 && precision != MCF_FP64) || max_slots < 1 || max_slots > MCF_POOL_MAX_SLOTS ||
+        check_every < 1)
+        return MCF_E_ARG;
+    mcf_pool *p = new (std::nothrow) mcf_pool();
+    if (!p) return MCF_E_NOMEM;
+    p->device = device;
+    p->precision = precision;
+    p->budget = hbm_budget;
+    p->max_slots = max_slots;
+    p->check_every = check_every;
+    p->slot.assign(max_slots, nullptr);
+    p->desc.assign(max_slots, SlotDesc<double>{});
+    int rc = MCF_OK;
+    if (hipSetDevice(device) != hipSuccess) rc = MCF_E_DEVICE;
+    if (!rc) {
+        if (stream) p->stream = (hipStream_t)stream;
+        else if (hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking) == hipSuccess) p->own_stream = true;
+        else rc = MCF_E_DEVICE;
+    }
+    const size_t work_cap = (size_t)max_slots * FUSED_MAX_N;
+    if (!rc && (hipMalloc((void **)&p->d_desc, sizeof(SlotDesc<double>) * max_slots) != hipSuccess ||
+                hipMalloc((void **)&p->d_work, sizeof(int2) * work_cap) != hipSuccess ||
+                hipMalloc((void **)&p->d_snap, sizeof(DevScalars) * max_slots) != hipSuccess))
+        rc = MCF_E_NOMEM;
+    if (!rc && (hipHostMalloc((void **)&p->h_snap, sizeof(DevScalars) * max_slots, hipHostMallocDefault) != hipSuccess ||
+                hipHostMalloc((void **)&p->h_desc, sizeof(SlotDesc<double>) * max_slots, hipHostMallocDefault) !=
+                    hipSuccess ||
+                hipHostMalloc((void **)&p->h_work, sizeof(int2) * work_cap, hipHostMallocDefault) != hipSuccess))
+        rc = MCF_E_NOMEM;
+    if (!rc && hipEventCreateWithFlags(&p->done, hipEventDisableTiming) != hipSuccess) rc = MCF_E_DEVICE;
+    if (!rc) rc = pool_upload(p);
+    if (rc) {
+        mcf_pool_destroy(p);
+        return rc;
+    }
+    *out = p;
+    return MCF_OK;
+}
+
+void mcf_pool_destroy(mcf_pool *p)
+{
+    if (!p) return;
+    if (p->pending) (void)mcf_pool_sync(p);  // refreshes every slot's state
+    if (p->stream) (void)hipStreamSynchronize(p->stream);
+    for (int sl = 0; sl < p->max_slots; ++sl)
+        if (p->slot[sl]) {
+            p->slot[sl]->pool = nullptr;
+            p->slot[sl]->pool_slot = -1;
+        }
+    if (p->done) (void)hipEventDestroy(p->done);
+    if (p->d_desc) (void)hipFree(p->d_desc);
+    if (p->d_work) (void)hipFree(p->d_work);
+    if (p->d_snap) (void)hipFree(p->d_snap);
+    if (p->h_snap) (void)hipHostFree(p->h_snap);
+    if (p->h_desc) (void)hipHostFree(p->h_desc);
+    if (p->h_work) (void)hipHostFree(p->h_work);
+    if (p->own_stream && p->stream) (void)hipStreamDestroy(p->stream);
+    delete p;
+}
+
+int mcf_pool_admit(mcf_pool *p, mcf_solver *s, int32_t *slot)
+{
+    if (!p || !s) return MCF_E_ARG;
+    if (s->pool || s->precision != p->precision || !s->c.fused) return MCF_E_ARG;
+    if (s->state == MCF_CONVERGED || s->state == MCF_DIVERGED) return MCF_E_STATE;
+    int rc = mcf_pool_sync(p);
+    if (rc) return rc;
+    if (p->budget && p->used + s->plan.total > p->budget) return MCF_E_NOMEM;
+    int sl = -1;
+    for (int q = 0; q < p->max_slots && sl < 0; ++q)
+        if (!p->slot[q]) sl = q;
+    if (sl < 0) return MCF_E_NOMEM;
+    MCF_TRY(hipStreamSynchronize(s->stream));
+    if ((rc = pull_scalars(s))) return rc;
+    s->hs->stop = 0;
+    s->hs->state = MCF_RUNNING;
+    s->hs->stop_enabled = 1;
+    if ((rc = push_scalars(s))) return rc;
+    MCF_TRY(hipStreamSynchronize(s->stream));
+    SlotDesc<double> &d = p->desc[sl];
+    d.c = s->c;
+    d.b = s->bufs<double>();  // pointers only: the same layout serves FP32 instances
+    d.pl = s->pl;
+    d.G0 = p->G;
+    d.k0 = s->k;
+    d.max_iter = s->opt.max_iter;
+    d.par0 = s->parity(s->k);
+    d.active = 1;
+    p->slot[sl] = s;
+    p->used += s->plan.total;
+    s->pool = p;
+    s->pool_slot = sl;
+    s->state = MCF_RUNNING;
+    if ((rc = pool_upload(p))) return rc;
+    p->h_snap[sl] = *s->hs;
+    if (slot) *slot = sl;
+    return MCF_OK;
+}
+
+int mcf_pool_step(mcf_pool *p, int32_t iters)
+{
+    if (!p || iters < 1) return MCF_E_ARG;
+    int rc = mcf_pool_sync(p);
+    if (rc) return rc;
+    if (p->nwork == 0) return MCF_OK;
+    const int ns = p->max_slots;
+    for (int it = 0; it < iters; ++it) {
+        const bool check = it == iters - 1;
+        bool adapt = false;
+        for (int sl = 0; sl < ns; ++sl) {
+            const SlotDesc<double> &d = p->desc[sl];
+            if (!d.active || d.c.k_adapt <= 0) continue;
+            const long long k = d.k0 + (p->G - d.G0);
+            if (k < d.max_iter && k % d.c.k_adapt == 0) adapt = true;
+        }
+        hipError_t e;
+        if (p->precision == MCF_FP32)
+            e = launch_pool_iteration<float>((const SlotDesc<float> *)p->d_desc, p->d_work, p->nwork, ns, p->max_m,
+                                             p->max_ept, p->G, check, check || adapt, p->stream);
+        else
+            e = launch_pool_iteration<double>(p->d_desc, p->d_work, p->nwork, ns, p->max_m, p->max_ept, p->G, check,
+                                              check || adapt, p->stream);
+        MCF_TRY(e);
+        p->G += 1;
+    }
+    if (p->precision == MCF_FP32)
+        MCF_TRY(launch_pool_gather<float>((const SlotDesc<float> *)p->d_desc, ns, p->d_snap, p->stream));
+    else
+        MCF_TRY(launch_pool_gather<double>(p->d_desc, ns, p->d_snap, p->stream));
+    MCF_TRY(hipMemcpyAsync(p->h_snap, p->d_snap, sizeof(DevScalars) * ns, hipMemcpyDeviceToHost, p->stream));
+    MCF_TRY(hipEventRecord(p->done, p->stream));
+    p->pending = true;
+    return MCF_OK;
+}
+
+int mcf_pool_sync(mcf_pool *p)
+{
+    if (!p) return MCF_E_ARG;
+    if (!p->pending) return MCF_OK;
+    MCF_TRY(hipEventSynchronize(p->done));
+    p->pending = false;
+    for (int sl = 0; sl < p->max_slots; ++sl)
+        if (p->slot[sl]) pool_refresh(p, sl);
+    return MCF_OK;
+}
+
+int mcf_pool_poll(mcf_pool *p, int32_t slot, mcf_result *out)
+{
+    if (!p || slot < 0 || slot >= p->max_slots || !p->slot[slot] || !out) return MCF_E_ARG;
+    return mcf_status(p->slot[slot], out);
+}
+
+int mcf_pool_retire(mcf_pool *p, int32_t slot)
+{
+    if (!p || slot < 0 || slot >= p->max_slots || !p->slot[slot]) return MCF_E_ARG;
+    int rc = mcf_pool_sync(p);
+    if (rc) return rc;
+    MCF_TRY(hipStreamSynchronize(p->stream));
+    mcf_solver *s = p->slot[slot];
+    pool_refresh(p, slot);
+    p->desc[slot].active = 0;
+    p->slot[slot] = nullptr;
+    p->used -= s->plan.total;
+    s->pool = nullptr;
+    s->pool_slot = -1;
+    return pool_upload(p);
+}
+
+int mcf_pool_info(const mcf_pool *p, int32_t *active, size_t *used_bytes, int64_t *iterations)
+{
+    if (!p) return MCF_E_ARG;
+    int a = 0;
+    for (int sl = 0; sl < p->max_slots; ++sl) a += p->slot[sl] != nullptr;
+    if (active) *active = a;
+    if (used_bytes) *used_bytes = p->used;
+    if (iterations) *iterations = p->G;
+    return MCF_OK;
+}
 }  // extern "C"

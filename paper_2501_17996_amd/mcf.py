@@ -33,7 +33,10 @@ EXPORTED = [
     "mcf_options_default", "mcf_workspace_bytes", "mcf_create", "mcf_solve", "mcf_run", "mcf_reset",
     "mcf_status", "mcf_get_solution", "mcf_get_state", "mcf_set_state", "mcf_destroy", "mcf_strerror",
     "mcf_debug_poison", "mcf_enable_kernel_timing", "mcf_kernel_time", "mcf_layout",
+    "mcf_pool_create", "mcf_pool_admit", "mcf_pool_step", "mcf_pool_sync", "mcf_pool_poll", "mcf_pool_retire",
+    "mcf_pool_info", "mcf_pool_destroy",
 ]
+MCF_POOL_MAX_SLOTS = 256
 
 
 class mcf_options(ctypes.Structure):
@@ -98,6 +101,16 @@ def lib():
         L.mcf_enable_kernel_timing.argtypes = [_vp, ctypes.c_int32]
         L.mcf_kernel_time.argtypes = [_vp, _dp, ctypes.POINTER(ctypes.c_int64)]
         L.mcf_layout.argtypes = [_vp, _ip, _ip, _ip, _ip]
+        L.mcf_pool_create.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_size_t, ctypes.c_int32, ctypes.c_int32,
+                                      _vp, ctypes.POINTER(_vp)]
+        L.mcf_pool_admit.argtypes = [_vp, _vp, _ip]
+        L.mcf_pool_step.argtypes = [_vp, ctypes.c_int32]
+        L.mcf_pool_sync.argtypes = [_vp]
+        L.mcf_pool_poll.argtypes = [_vp, ctypes.c_int32, ctypes.POINTER(mcf_result)]
+        L.mcf_pool_retire.argtypes = [_vp, ctypes.c_int32]
+        L.mcf_pool_info.argtypes = [_vp, _ip, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_int64)]
+        L.mcf_pool_destroy.argtypes = [_vp]
+        L.mcf_pool_destroy.restype = None
         _lib = L
     return _lib
 
@@ -222,6 +235,7 @@ class Solver:
         if stream is not None:
             o.stream = int(stream)
         self.n, self.m = int(inst.n), int(inst.m)
+        self.workspace = kw.get("workspace")
         self.opt = o
         self.h = mcf_create(inst.n, inst.tail, inst.head, inst.cap, inst.utility, inst.gamma, inst.w, o)
 
@@ -264,3 +278,86 @@ class Solver:
 
     def layout(self) -> dict:
         return mcf_layout(self.h)
+
+
+# ------------------------------------------------------------------- batching pool
+def mcf_pool_create(precision: int, hbm_budget: int = 0, max_slots: int = 64, check_every: int = 20,
+                    stream=None, device: int = 0):
+    h = _vp()
+    _check(lib().mcf_pool_create(int(device), int(precision), int(hbm_budget), int(max_slots), int(check_every),
+                                 stream, ctypes.byref(h)), "mcf_pool_create")
+    return h
+
+
+def mcf_pool_admit(p, s) -> int:
+    slot = ctypes.c_int32()
+    _check(lib().mcf_pool_admit(p, s, ctypes.byref(slot)), "mcf_pool_admit")
+    return slot.value
+
+
+def mcf_pool_step(p, iters: int):
+    _check(lib().mcf_pool_step(p, int(iters)), "mcf_pool_step")
+
+
+def mcf_pool_sync(p):
+    _check(lib().mcf_pool_sync(p), "mcf_pool_sync")
+
+
+def mcf_pool_poll(p, slot: int) -> dict:
+    r = mcf_result()
+    _check(lib().mcf_pool_poll(p, int(slot), ctypes.byref(r)), "mcf_pool_poll")
+    return r.as_dict()
+
+
+def mcf_pool_retire(p, slot: int):
+    _check(lib().mcf_pool_retire(p, int(slot)), "mcf_pool_retire")
+
+
+def mcf_pool_info(p) -> dict:
+    a, u, g = ctypes.c_int32(), ctypes.c_size_t(), ctypes.c_int64()
+    _check(lib().mcf_pool_info(p, ctypes.byref(a), ctypes.byref(u), ctypes.byref(g)), "mcf_pool_info")
+    return {"active": a.value, "used_bytes": u.value, "iterations": g.value}
+
+
+def mcf_pool_destroy(p):
+    if p:
+        lib().mcf_pool_destroy(p)
+
+
+class Pool:
+    """A batching pool: many instances advanced by one launch per iteration."""
+
+    def __init__(self, precision: int = MCF_FP32, hbm_budget: int = 0, max_slots: int = 64, check_every: int = 20,
+                 stream=None):
+        self.check_every = int(check_every)
+        self.h = mcf_pool_create(precision, hbm_budget, max_slots, check_every,
+                                 ctypes.c_void_p(int(stream)) if stream is not None else None)
+
+    def admit(self, solver: "Solver") -> int:
+        return mcf_pool_admit(self.h, solver.h)
+
+    def step(self, iters: int | None = None):
+        mcf_pool_step(self.h, iters or self.check_every)
+
+    def sync(self):
+        mcf_pool_sync(self.h)
+
+    def poll(self, slot: int) -> dict:
+        return mcf_pool_poll(self.h, slot)
+
+    def retire(self, slot: int):
+        mcf_pool_retire(self.h, slot)
+
+    def info(self) -> dict:
+        return mcf_pool_info(self.h)
+
+    def close(self):
+        if getattr(self, "h", None):
+            mcf_pool_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,226 @@
+"""Continuous-batching serving loop for MCF requests on one GPU.
+
+Requests (an instance and an arrival time) are admitted into a batching pool
+(``mcf_pool_*``) as slots and device memory free up.  Every pool step advances
+all admitted instances together -- one kernel launch per iteration for all of
+them -- and ends with a residual check of each.  Converged instances are retired
+at once, their memory is returned, and queued requests take their place while
+the others keep iterating.
+
+Device memory comes from one arena (a torch allocation) that the loop
+sub-allocates first-fit: admission is by HBM footprint (``mcf_workspace_bytes``),
+and no device allocation happens while serving.
+
+The loop is written against a small backend interface (footprint, create,
+admit, step, sync, poll, retire, destroy) so that its bookkeeping can be tested
+with a CPU stand-in.
+"""
+from __future__ import annotations
+
+import math
+import time
+from collections import deque
+from dataclasses import dataclass, field
+
+ALIGN = 256
+
+
+@dataclass
+class Request:
+    rid: int
+    arrival: float          # seconds from the start of the run
+    inst: object            # instances.Instance
+
+
+@dataclass
+class Record:
+    rid: int
+    n: int
+    m: int
+    arrival: float
+    admitted: float = math.nan
+    done: float = math.nan
+    iters: int = 0
+    state: str = ""
+    rel_kkt: float = math.nan
+    primal_obj: float = math.nan
+    slot: int = -1
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def latency(self) -> float:
+        return self.done - self.arrival
+
+    @property
+    def service(self) -> float:
+        return self.done - self.admitted
+
+
+class Arena:
+    """First-fit allocator of byte ranges inside one device allocation."""
+
+    def __init__(self, nbytes: int):
+        self.size = int(nbytes)
+        self.free = [(0, self.size)]   # sorted, disjoint (offset, length)
+
+    def alloc(self, nbytes: int):
+        need = (int(nbytes) + ALIGN - 1) // ALIGN * ALIGN
+        for k, (off, ln) in enumerate(self.free):
+            if ln >= need:
+                if ln == need:
+                    self.free.pop(k)
+                else:
+                    self.free[k] = (off + need, ln - need)
+                return off, need
+        return None
+
+    def release(self, off: int, ln: int):
+        self.free.append((off, ln))
+        self.free.sort()
+        merged = []
+        for o, l in self.free:
+            if merged and merged[-1][0] + merged[-1][1] == o:
+                merged[-1] = (merged[-1][0], merged[-1][1] + l)
+            else:
+                merged.append((o, l))
+        self.free = merged
+
+    def free_bytes(self) -> int:
+        return sum(l for _, l in self.free)
+
+
+class GpuBackend:
+    """libmcf batching pool with instance workspaces carved from one torch allocation."""
+
+    def __init__(self, precision: int, hbm_budget: int, max_slots: int, check_every: int, tol: float,
+                 max_iter: int = 200000):
+        import torch
+
+        from . import mcf
+        self.mcf = mcf
+        self.torch = torch
+        self.precision, self.tol, self.max_iter = precision, tol, max_iter
+        self.check_every = check_every
+        self.buf = torch.empty(int(hbm_budget), dtype=torch.uint8, device="cuda")
+        self.base = self.buf.data_ptr()
+        self.arena = Arena(hbm_budget)
+        self.setup_stream = torch.cuda.Stream()
+        self.pool = mcf.Pool(precision, hbm_budget, max_slots, check_every)
+        self.max_slots = max_slots
+
+    def footprint(self, inst) -> int:
+        return self.mcf.mcf_workspace_bytes(inst.n, inst.m, self.precision)
+
+    def create(self, inst):
+        got = self.arena.alloc(self.footprint(inst))
+        if got is None:
+            return None
+        off, ln = got
+        s = self.mcf.Solver(inst, precision=self.precision, tol=self.tol, max_iter=self.max_iter,
+                            check_every=self.check_every, stream=self.setup_stream.cuda_stream,
+                            workspace=self.base + off, workspace_bytes=ln)
+        s.arena_block = got
+        return s
+
+    def admit(self, h) -> int:
+        return self.pool.admit(h)
+
+    def step(self):
+        self.pool.step(self.check_every)
+
+    def sync(self):
+        self.pool.sync()
+
+    def poll(self, slot: int) -> dict:
+        return self.pool.poll(slot)
+
+    def retire(self, slot: int):
+        self.pool.retire(slot)
+
+    def destroy(self, h):
+        block = h.arena_block
+        h.close()
+        self.arena.release(*block)
+
+    def close(self):
+        self.pool.close()
+
+
+def percentile(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return math.nan
+    k = (len(xs) - 1) * q / 100.0
+    lo, hi = int(math.floor(k)), int(math.ceil(k))
+    return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
+
+
+def serve(requests, backend, clock=time.perf_counter, keep=None, idle_wait=1e-4):
+    """Runs the request stream to completion.  ``requests`` are sorted by arrival.
+    ``keep(record, handle)`` may read a finished instance (its solution) before it is
+    destroyed.  Returns (records, summary)."""
+    pending = deque(sorted(requests, key=lambda r: r.arrival))
+    queue = deque()
+    active = {}                      # slot -> (request, handle, record)
+    records = []
+    t0 = clock()
+    steps = 0
+    updates = 0.0
+    while pending or queue or active:
+        now = clock() - t0
+        while pending and pending[0].arrival <= now:
+            queue.append(pending.popleft())
+        # admission: FIFO, while a slot and device memory are free
+        while queue and len(active) < backend.max_slots:
+            req = queue[0]
+            h = backend.create(req.inst)
+            if h is None:
+                break
+            slot = backend.admit(h)
+            rec = Record(req.rid, req.inst.n, req.inst.m, req.arrival, admitted=clock() - t0, slot=slot)
+            active[slot] = (req, h, rec)
+            queue.popleft()
+        if not active:
+            if pending:
+                wait = pending[0].arrival - (clock() - t0)
+                if wait > 0:
+                    time.sleep(min(wait, 0.01) if wait > idle_wait else 0)
+            continue
+        before = {slot: backend.poll(slot)["iters"] for slot in active}
+        backend.step()
+        backend.sync()
+        steps += 1
+        t_done = clock() - t0
+        for slot in list(active):
+            req, h, rec = active[slot]
+            st = backend.poll(slot)
+            updates += float(req.inst.n) * req.inst.m * (st["iters"] - before[slot])
+            if st["state_name"] == "running":
+                continue
+            backend.retire(slot)
+            rec.done = t_done
+            rec.iters = st["iters"]
+            rec.state = st["state_name"]
+            rec.rel_kkt = st["rel_kkt"]
+            rec.primal_obj = st["primal_obj"]
+            if keep is not None:
+                keep(rec, h)
+            backend.destroy(h)
+            records.append(rec)
+            del active[slot]
+    makespan = clock() - t0
+    lat = [r.latency for r in records]
+    svc = [r.service for r in records]
+    summary = {
+        "requests": len(records),
+        "makespan_s": makespan,
+        "instances_per_s": len(records) / makespan if makespan > 0 else math.nan,
+        "edge_dest_updates_per_s": updates / makespan if makespan > 0 else math.nan,
+        "latency_p50_s": percentile(lat, 50),
+        "latency_p99_s": percentile(lat, 99),
+        "service_p50_s": percentile(svc, 50),
+        "service_p99_s": percentile(svc, 99),
+        "steps": steps,
+        "converged": sum(r.state == "converged" for r in records),
+    }
+    return records, summary

@@ -102,3 +102,10 @@ def test_graph_not_strongly_connected(mcf):
     with pytest.raises(mcf.MCFError) as ei:
         mcf.mcf_create(3, tail, head, np.ones(3), 0, 0.0, w)
     assert ei.value.code == mcf.MCF_E_GRAPH
+
+
+def test_pool_argument_validation(mcf):
+    for args in [(7, 0, 4, 20), (1, 0, 0, 20), (1, 0, mcf.MCF_POOL_MAX_SLOTS + 1, 20), (1, 0, 4, 0)]:
+        with pytest.raises(mcf.MCFError) as ei:
+            mcf.mcf_pool_create(args[0], args[1], args[2], args[3])
+        assert ei.value.code == mcf.MCF_E_ARG
