@@ -88,6 +88,57 @@ def cpu_baseline(inst, tol, check_every, budget_s: float):
                       f"{check_every}), FP64, {dt:.1f} s on {threads} threads"}
 
 
+def serve_bench(args):
+    """Serving stream: requests r = 0.. (seed 1000+r; n ~ U{20..500}, out-degree ~ U{4..16},
+    log or power(0.5) utility), FP32 iterates batched in one pool, Poisson arrivals at
+    `load` x the throughput of a saturated calibration run.  Reports p50/p99 latency and
+    throughput, beside the FP64 single-instance solve of the first requests one at a time."""
+    import torch
+    from paper_2501_17996_amd import instances as I
+    from paper_2501_17996_amd import mcf
+    from paper_2501_17996_amd.serve import GpuBackend, Request, serve
+
+    torch.cuda.set_device(0)
+    tol, K = 1e-4, args.check_every
+
+    def stream(count, rate, offset=0):
+        times = I.poisson_arrivals(count, rate, seed=7) if rate > 0 else [0.0] * count
+        return [Request(r, float(t), (lambda r=r: I.serving_request(r))) for r, t in zip(range(offset, offset + count), times)]
+
+    budget = int(args.serve_budget_gb * 2 ** 30)
+    be = GpuBackend(mcf.MCF_FP32, budget, args.slots, K, tol, max_iter=args.serve_max_iter)
+    _, calib = serve(stream(args.calib, 0.0, offset=args.requests), be)
+    rate = args.load * calib["instances_per_s"]
+    records, summ = serve(stream(args.requests, rate), be)
+    be.close()
+    # the plain FP64 single-instance solve, one request after another
+    n_single = min(args.single, args.requests)
+    t0, upd = time.perf_counter(), 0.0
+    for r in range(n_single):
+        inst = I.serving_request(r)
+        S = mcf.Solver(inst, precision=mcf.MCF_FP64, tol=tol, check_every=K, max_iter=args.serve_max_iter)
+        st = S.solve()
+        upd += inst.n * inst.m * st["iters"]
+        S.close()
+    t_single = time.perf_counter() - t0
+    out = {
+        "metric": "served MCF instances/s (FP32 batched pool, rel KKT 1e-4)",
+        "value": summ["instances_per_s"], "unit": "instances/s", "n_gpus": 1, "higher_is_better": True,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{args.requests} requests seed 1000+r, n~U{{20..500}}, out-degree~U{{4..16}}, "
+                               f"log/power(0.5), Poisson arrivals at {args.load} x saturated throughput",
+                   "slots": args.slots, "check_every": K, "hbm_budget_gb": args.serve_budget_gb,
+                   "arrival_rate_per_s": rate, "calibration": calib},
+        "latency_p50_s": summ["latency_p50_s"], "latency_p99_s": summ["latency_p99_s"],
+        "service_p50_s": summ["service_p50_s"], "service_p99_s": summ["service_p99_s"],
+        "edge_dest_updates_per_s": summ["edge_dest_updates_per_s"], "converged": summ["converged"],
+        "requests": summ["requests"], "makespan_s": summ["makespan_s"],
+        "single_fp64": {"requests": n_single, "instances_per_s": n_single / t_single,
+                        "edge_dest_updates_per_s": upd / t_single},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -103,10 +154,21 @@ def main():
                     help="run one 256 MiB device copy first (a counter reference of known size)")
     ap.add_argument("--iters", type=int, default=0,
                     help="run this many iterations per step instead of a full solve (large workloads)")
+    ap.add_argument("--requests", type=int, default=2000, help="serving workload: stream length")
+    ap.add_argument("--calib", type=int, default=200, help="serving workload: saturated calibration requests")
+    ap.add_argument("--load", type=float, default=0.8, help="serving workload: arrival rate / saturated rate")
+    ap.add_argument("--slots", type=int, default=64, help="serving workload: pool slots")
+    ap.add_argument("--single", type=int, default=50, help="serving workload: FP64 single-instance comparison size")
+    ap.add_argument("--serve-budget-gb", type=float, default=16.0)
+    ap.add_argument("--serve-max-iter", type=int, default=60000)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         raise SystemExit(2)
+
+    if args.workload == "serve":
+        serve_bench(args)
+        return
 
     import torch
     from paper_2501_17996_amd import mcf

@@ -29,7 +29,12 @@ ALIGN = 256
 class Request:
     rid: int
     arrival: float          # seconds from the start of the run
-    inst: object            # instances.Instance
+    inst: object            # instances.Instance, or a callable that builds it on first use
+
+    def instance(self):
+        if callable(self.inst):
+            self.inst = self.inst()
+        return self.inst
 
 
 @dataclass
@@ -173,11 +178,12 @@ def serve(requests, backend, clock=time.perf_counter, keep=None, idle_wait=1e-4)
         # admission: FIFO, while a slot and device memory are free
         while queue and len(active) < backend.max_slots:
             req = queue[0]
-            h = backend.create(req.inst)
+            inst = req.instance()
+            h = backend.create(inst)
             if h is None:
                 break
             slot = backend.admit(h)
-            rec = Record(req.rid, req.inst.n, req.inst.m, req.arrival, admitted=clock() - t0, slot=slot)
+            rec = Record(req.rid, inst.n, inst.m, req.arrival, admitted=clock() - t0, slot=slot)
             active[slot] = (req, h, rec)
             queue.popleft()
         if not active:
@@ -194,7 +200,7 @@ def serve(requests, backend, clock=time.perf_counter, keep=None, idle_wait=1e-4)
         for slot in list(active):
             req, h, rec = active[slot]
             st = backend.poll(slot)
-            updates += float(req.inst.n) * req.inst.m * (st["iters"] - before[slot])
+            updates += float(rec.n) * rec.m * (st["iters"] - before[slot])
             if st["state_name"] == "running":
                 continue
             backend.retire(slot)
@@ -206,6 +212,7 @@ def serve(requests, backend, clock=time.perf_counter, keep=None, idle_wait=1e-4)
             if keep is not None:
                 keep(rec, h)
             backend.destroy(h)
+            req.inst = None          # the library holds its own copy; free the host arrays
             records.append(rec)
             del active[slot]
     makespan = clock() - t0

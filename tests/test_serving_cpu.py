@@ -61,9 +61,9 @@ def test_serving_loop_admission_and_completion():
 
 def test_serving_results_do_not_depend_on_the_mix():
     """Each request gets the same result whatever else is batched with it."""
-    reqs = _stream(10, seed=5)
     out = {}
     for slots in (1, 5):
+        reqs = _stream(10, seed=5)      # the loop releases each instance once it is served
         be = OracleBackend(budget=1 << 40, max_slots=slots, check_every=10, tol=1e-5)
         records, _ = serve(reqs, be)
         out[slots] = {r.rid: (r.iters, r.primal_obj) for r in records}
