@@ -63,6 +63,8 @@ typedef struct {
     void *stream;           /* hipStream_t to run on, or NULL for a stream owned by the handle */
     void *workspace;        /* optional caller device memory (>= mcf_workspace_bytes), or NULL */
     size_t workspace_bytes;
+    int64_t adapt_until;    /* omega is adapted only while k < adapt_until (-1: always).  Section 2.4 notes that
+                               freezing omega after some iterations restores the constant-omega convergence proof */
 } mcf_options;
 
 /* Latest solve record.  Residuals are those of the last checked iteration:
@@ -89,7 +91,8 @@ typedef struct {
 } mcf_scalars;
 
 /* Fills *o with the defaults: tol 1e-4, REL_KKT, FP64, check_every 1, max_iter 100000,
- * k_adapt 100, rho 1.9, theta 0.5, tau 1e-5, omega0 1, device 0, no stream, no workspace. */
+ * k_adapt 100, rho 1.9, theta 0.5, tau 1e-5, omega0 1, adapt_until -1, device 0, no stream,
+ * no workspace. */
 void mcf_options_default(mcf_options *o);
 
 /* Device bytes one instance needs at this precision with the kernel organisation AUTO picks

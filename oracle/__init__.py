@@ -52,7 +52,7 @@ def lib():
             build()
         L = ctypes.CDLL(_LIB)
         L.orc_create.restype = _vp
-        L.orc_create.argtypes = [_i32, _i32, _ip, _ip, _dp, _i32, _d, _dp, _d, _d, _d, _d, _i32, _i32]
+        L.orc_create.argtypes = [_i32, _i32, _ip, _ip, _dp, _i32, _d, _dp, _d, _d, _d, _d, _i32, _i32, _i64]
         L.orc_destroy.argtypes = [_vp]
         L.orc_reset.argtypes = [_vp]
         L.orc_step.argtypes = [_vp, _i32]
@@ -151,7 +151,7 @@ def num_threads_available() -> int:
 class OracleSolver:
     """FP64 PDMCF (Algorithm 2.1) on one instance."""
 
-    def __init__(self, inst, rho=1.9, theta=0.5, tau=1e-5, omega0=1.0, k_adapt=100, threads=1):
+    def __init__(self, inst, rho=1.9, theta=0.5, tau=1e-5, omega0=1.0, k_adapt=100, threads=1, adapt_until=-1):
         self.n, self.m = int(inst.n), int(inst.m)
         self._tail, self._head = _i32a(inst.tail), _i32a(inst.head)
         self._cap, self._w = _f64(inst.cap), _f64(inst.w)
@@ -159,7 +159,7 @@ class OracleSolver:
         self.threads = int(threads)
         h = lib().orc_create(self.n, self.m, _p(self._tail, _ip), _p(self._head, _ip), _p(self._cap),
                              self.utility, self.gamma, _p(self._w), float(rho), float(theta), float(tau),
-                             float(omega0), int(k_adapt), self.threads)
+                             float(omega0), int(k_adapt), self.threads, int(adapt_until))
         if not h:
             raise MemoryError("oracle allocation failed")
         self._h = ctypes.c_void_p(h)

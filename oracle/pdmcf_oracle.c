@@ -54,6 +54,7 @@ typedef struct orc_solver {
     double *w;
     double rho, theta, tau, omega0, eta;
     int32_t k_adapt, nthreads;
+    int64_t adapt_until; /* omega adapts only while k < adapt_until (< 0: always) */
     /* iterate state: F^{k-1/2}, Y^k, omega^k, step sizes, k */
     double *F, *Y;
     double omega, alpha, beta;
@@ -285,7 +286,7 @@ void orc_destroy(orc_solver *s)
 
 orc_solver *orc_create(int32_t n, int32_t m, const int32_t *tail, const int32_t *head, const double *cap,
                        int32_t utility, double gamma, const double *w, double rho, double theta, double tau,
-                       double omega0, int32_t k_adapt, int32_t nthreads)
+                       double omega0, int32_t k_adapt, int32_t nthreads, int64_t adapt_until)
 {
     if (n < 2 || m < 1) return NULL;
     orc_solver *s = (orc_solver *)calloc(1, sizeof(orc_solver));
@@ -302,6 +303,7 @@ orc_solver *orc_create(int32_t n, int32_t m, const int32_t *tail, const int32_t 
     s->utility = utility; s->gamma = gamma;
     s->rho = rho; s->theta = theta; s->tau = tau; s->omega0 = omega0;
     s->k_adapt = k_adapt; s->nthreads = nthreads > 0 ? nthreads : 1;
+    s->adapt_until = adapt_until;
     s->eta = orc_eta(n, m, tail, head);
     s->F = (double *)xcalloc(nm, sizeof(double));
     s->Q = (double *)xcalloc(nm, sizeof(double));
@@ -485,8 +487,10 @@ void orc_step(orc_solver *s, int32_t check)
     double *t = s->F; s->F = s->Fnew; s->Fnew = t;
     t = s->Y; s->Y = s->Ynew; s->Ynew = t;
     /* Algorithm 2.1 step 3: adapt omega when k is a multiple of k_adapt (k = 0 included)
-     * and both step norms exceed tau. */
-    if (s->k_adapt > 0 && s->k % s->k_adapt == 0 && dF > s->tau && dY > s->tau) {
+     * and both step norms exceed tau; optionally only before iteration adapt_until, the
+     * freeze Section 2.4 allows. */
+    if (s->k_adapt > 0 && s->k % s->k_adapt == 0 && (s->adapt_until < 0 || s->k < s->adapt_until) &&
+        dF > s->tau && dY > s->tau) {
         s->omega = pow(dY / dF, s->theta) * pow(s->omega, 1.0 - s->theta);
         s->alpha = s->eta / s->omega;
         s->beta = s->eta * s->omega;

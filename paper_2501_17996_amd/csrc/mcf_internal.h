@@ -28,11 +28,19 @@ struct Consts {
     int utility;           // 0 log, 1 power
     double gamma, c1, rho, theta, tau, tol;
     int k_adapt, stop_rule;
+    long long adapt_until;  // omega adapts only while k < adapt_until (< 0: always)
     int nblk_node;         // node-phase blocks (partials per quantity)
     int node_block;        // threads per node-phase block (64 or 256)
     int fused;             // 1: node-centric single-launch iteration (n <= FUSED_MAX_N)
     int nep, nnp;          // partials per edge quantity (dF, e, sup) and per node quantity
 };
+
+// Algorithm 2.1 step 3 adapts omega at iterations k that are multiples of k_adapt (k = 0
+// included), here also limited to k < adapt_until when that is set.
+__host__ __device__ inline bool adapts_at(const Consts &c, long long k)
+{
+    return c.k_adapt > 0 && k % c.k_adapt == 0 && (c.adapt_until < 0 || k < c.adapt_until);
+}
 
 // Largest n served by the node-centric fused iteration (one wave per edge column).
 constexpr int FUSED_MAX_N = 512;

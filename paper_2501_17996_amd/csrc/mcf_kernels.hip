@@ -966,7 +966,7 @@ __global__ __launch_bounds__(64 * POOL_WAVES) void pool_fused_kernel(const SlotD
     long long k;
     if (!slot_live(d, G, k)) return;
     const int parity = d.par0 ^ (int)((G - d.G0) & 1);
-    const bool partial = CHECK || (d.c.k_adapt > 0 && k % d.c.k_adapt == 0);
+    const bool partial = CHECK || adapts_at(d.c, k);
     const int n = d.c.n;
     if (n <= 64) pool_util<T, 1, CHECK>(d, parity, wk.y, partial, vsh, red);
     else if (n <= 128) pool_util<T, 2, CHECK>(d, parity, wk.y, partial, vsh, red);
@@ -994,7 +994,7 @@ __global__ __launch_bounds__(CTRL_BLOCK) void pool_control_kernel(const SlotDesc
     const SlotDesc<T> &d = slots[blockIdx.x];
     long long k;
     if (!slot_live(d, G, k)) return;
-    const bool adapt = d.c.k_adapt > 0 && k % d.c.k_adapt == 0;
+    const bool adapt = adapts_at(d.c, k);
     if (!check && !adapt) return;
     control_body<T>(d.c, d.b, d.pl, check, adapt, k + 1, lds);
 }

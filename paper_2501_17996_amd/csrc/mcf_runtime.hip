@@ -331,11 +331,10 @@ template <typename T>
 int enqueue_block(mcf_solver *s, long long k0, long long count)
 {
     const Bufs<T> b = s->bufs<T>();
-    const int ka = s->opt.k_adapt;
     for (long long it = 0; it < count; ++it) {
         const long long k = k0 + it;
         const bool check = it == count - 1;
-        const bool adapt = ka > 0 && k % ka == 0;
+        const bool adapt = adapts_at(s->c, k);
         const bool partial = check || adapt;
         hipEvent_t e0 = nullptr, e1 = nullptr;
         const bool timed = s->timing && k % TIMING_STRIDE == 0;
@@ -481,6 +480,7 @@ void mcf_options_default(mcf_options *o)
     o->theta = 0.5;
     o->tau = 1e-5;
     o->omega0 = 1.0;
+    o->adapt_until = -1;
     o->device = 0;
 }
 
@@ -569,6 +569,7 @@ int mcf_create(int32_t n, int32_t m, const int32_t *tail, const int32_t *head, c
     c.tau = o.tau;
     c.tol = o.tol;
     c.k_adapt = o.k_adapt;
+    c.adapt_until = o.adapt_until;
     c.stop_rule = o.stop_rule;
     c.nblk_node = node_blocks(n);
     c.node_block = node_block_for(n);
@@ -974,9 +975,9 @@ int mcf_pool_step(mcf_pool *p, int32_t iters)
         bool adapt = false;
         for (int sl = 0; sl < ns; ++sl) {
             const SlotDesc<double> &d = p->desc[sl];
-            if (!d.active || d.c.k_adapt <= 0) continue;
+            if (!d.active) continue;
             const long long k = d.k0 + (p->G - d.G0);
-            if (k < d.max_iter && k % d.c.k_adapt == 0) adapt = true;
+            if (k < d.max_iter && adapts_at(d.c, k)) adapt = true;
         }
         hipError_t e;
         if (p->precision == MCF_FP32)

@@ -44,7 +44,8 @@ class mcf_options(ctypes.Structure):
                 ("stop_rule", ctypes.c_int32), ("check_every", ctypes.c_int32), ("k_adapt", ctypes.c_int32),
                 ("rho", ctypes.c_double), ("theta", ctypes.c_double), ("tau", ctypes.c_double),
                 ("omega0", ctypes.c_double), ("device", ctypes.c_int32), ("kernel_mode", ctypes.c_int32),
-                ("stream", ctypes.c_void_p), ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t)]
+                ("stream", ctypes.c_void_p), ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t),
+                ("adapt_until", ctypes.c_int64)]
 
 
 class mcf_result(ctypes.Structure):

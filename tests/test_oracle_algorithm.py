@@ -485,6 +485,10 @@ def test_adapt_period_and_threshold(orc):
     assert omegas[0] != 1.0 and changed == [3, 6]
     frozen = orc.OracleSolver(inst, tau=1e9)
     assert all(frozen.step(check=False)["omega"] == 1.0 for _ in range(5))
+    # the freeze of Section 2.4: no change at or after adapt_until
+    fz = orc.OracleSolver(inst, k_adapt=3, adapt_until=6)
+    om = [fz.step(check=False)["omega"] for _ in range(12)]
+    assert [k for k in range(1, 12) if om[k] != om[k - 1]] == [3]
 
 
 def test_paper_parameters_golden(orc):
