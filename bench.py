@@ -106,7 +106,8 @@ def serve_bench(args):
         return [Request(r, float(t), (lambda r=r: I.serving_request(r))) for r, t in zip(range(offset, offset + count), times)]
 
     budget = int(args.serve_budget_gb * 2 ** 30)
-    be = GpuBackend(mcf.MCF_FP32, budget, args.slots, K, tol, max_iter=args.serve_max_iter)
+    be = GpuBackend(mcf.MCF_FP32, budget, args.slots, K, tol, max_iter=args.serve_max_iter,
+                    adapt_until=args.adapt_until)
     _, calib = serve(stream(args.calib, 0.0, offset=args.requests), be)
     rate = args.load * calib["instances_per_s"]
     records, summ = serve(stream(args.requests, rate), be)
@@ -116,7 +117,8 @@ def serve_bench(args):
     t0, upd = time.perf_counter(), 0.0
     for r in range(n_single):
         inst = I.serving_request(r)
-        S = mcf.Solver(inst, precision=mcf.MCF_FP64, tol=tol, check_every=K, max_iter=args.serve_max_iter)
+        S = mcf.Solver(inst, precision=mcf.MCF_FP64, tol=tol, check_every=K, max_iter=args.serve_max_iter,
+                       adapt_until=args.adapt_until)
         st = S.solve()
         upd += inst.n * inst.m * st["iters"]
         S.close()
@@ -128,6 +130,7 @@ def serve_bench(args):
         "config": {"workload": f"{args.requests} requests seed 1000+r, n~U{{20..500}}, out-degree~U{{4..16}}, "
                                f"log/power(0.5), Poisson arrivals at {args.load} x saturated throughput",
                    "slots": args.slots, "check_every": K, "hbm_budget_gb": args.serve_budget_gb,
+                   "adapt_until": args.adapt_until,
                    "arrival_rate_per_s": rate, "calibration": calib},
         "latency_p50_s": summ["latency_p50_s"], "latency_p99_s": summ["latency_p99_s"],
         "service_p50_s": summ["service_p50_s"], "service_p99_s": summ["service_p99_s"],
@@ -161,14 +164,21 @@ def main():
     ap.add_argument("--single", type=int, default=50, help="serving workload: FP64 single-instance comparison size")
     ap.add_argument("--serve-budget-gb", type=float, default=16.0)
     ap.add_argument("--serve-max-iter", type=int, default=60000)
+    ap.add_argument("--adapt-until", type=int, default=None,
+                    help="freeze omega from this iteration on (Section 2.4); default: never for the solve "
+                         "workloads, 1000 for the serving stream")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         raise SystemExit(2)
 
     if args.workload == "serve":
+        if args.adapt_until is None:
+            args.adapt_until = 1000
         serve_bench(args)
         return
+    if args.adapt_until is None:
+        args.adapt_until = -1
 
     import torch
     from paper_2501_17996_amd import mcf
@@ -179,7 +189,7 @@ def main():
     s = 4 if prec == mcf.MCF_FP32 else 8
     stream = torch.cuda.current_stream()
     S = mcf.Solver(inst, precision=prec, tol=tol, check_every=args.check_every, max_iter=200000,
-                   stream=stream.cuda_stream, kernel_mode=args.kernel_mode)
+                   stream=stream.cuda_stream, kernel_mode=args.kernel_mode, adapt_until=args.adapt_until)
     if args.copy_calibration:
         src = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda").fill_(1.0)
         dst = torch.empty_like(src)
@@ -224,7 +234,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if prec == mcf.MCF_FP32 else "f64",
         "data": "synthetic",
-        "config": {"workload": desc, "n": n, "m": m, "precision": args.precision,
+        "config": {"workload": desc, "n": n, "m": m, "precision": args.precision, "adapt_until": args.adapt_until,
                    "reductions": "f64", "check_every": args.check_every, "tol": tol,
                    "iters_per_step": iters / args.steps, "final_rel_kkt": st["rel_kkt"],
                    "step": f"{args.iters} iterations from the cold start" if args.iters > 0 else "full solve",

@@ -98,13 +98,13 @@ class GpuBackend:
     """libmcf batching pool with instance workspaces carved from one torch allocation."""
 
     def __init__(self, precision: int, hbm_budget: int, max_slots: int, check_every: int, tol: float,
-                 max_iter: int = 200000):
+                 max_iter: int = 200000, adapt_until: int = -1):
         import torch
 
         from . import mcf
         self.mcf = mcf
         self.torch = torch
-        self.precision, self.tol, self.max_iter = precision, tol, max_iter
+        self.precision, self.tol, self.max_iter, self.adapt_until = precision, tol, max_iter, adapt_until
         self.check_every = check_every
         self.buf = torch.empty(int(hbm_budget), dtype=torch.uint8, device="cuda")
         self.base = self.buf.data_ptr()
@@ -123,7 +123,7 @@ class GpuBackend:
         off, ln = got
         s = self.mcf.Solver(inst, precision=self.precision, tol=self.tol, max_iter=self.max_iter,
                             check_every=self.check_every, stream=self.setup_stream.cuda_stream,
-                            workspace=self.base + off, workspace_bytes=ln)
+                            workspace=self.base + off, workspace_bytes=ln, adapt_until=self.adapt_until)
         s.arena_block = got
         return s
 

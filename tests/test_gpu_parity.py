@@ -97,6 +97,21 @@ def test_c1_trajectory_fp64_every_iteration(M, seed, mode):
     print(f"c1 seed {seed}: worst relative error over 700 iterations {worst:.2e}")
 
 
+@pytest.mark.parametrize("mode", [0, 1])
+def test_frozen_primal_weight_trajectory(M, mode):
+    """The freeze of Section 2.4 (adapt_until) on both kernel organisations."""
+    inst = I.config2(1)
+    S = gpu_solver(M, inst, kernel_mode=mode, adapt_until=250)
+    O = oracle.OracleSolver(inst, threads=THREADS, adapt_until=250)
+    done = 0
+    for k in (99, 101, 201, 301, 600):
+        S.run(k - done)
+        O.run(k - done, check=False)
+        done = k
+        assert_state_close(S, O, what=f"adapt_until k={k}")
+    assert S.status()["omega"] == pytest.approx(O.metrics()["omega"], rel=1e-12)
+
+
 @pytest.mark.parametrize("seed", [0, 1])
 def test_c1_solve_iterations_match_oracle(M, seed):
     inst = I.config1(seed)
