@@ -142,6 +142,73 @@ def serve_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def warmstart_bench(args):
+    """Section 3.1 warm start: for perturbation ratios nu, the perturbed problem is solved until
+    its iterate is feasible; the original problem then starts from that (F, Y, omega).  Reports
+    iterations and seconds of the original solve, cold and warm, on the config3-shaped
+    instance with n=1000 (the paper's warm-start study uses n=1000, q=10)."""
+    import torch
+    from paper_2501_17996_amd import instances as I
+    from paper_2501_17996_amd import mcf, warmstart
+
+    torch.cuda.set_device(0)
+    inst = I.ring_instance(1000, 10, seed=11)
+    prec = mcf.MCF_FP32 if args.precision == "fp32" else mcf.MCF_FP64
+
+    def make(i):
+        return mcf.Solver(i, precision=prec, tol=1e-4, check_every=10, max_iter=200000)
+
+    cold = make(inst)
+    t0 = time.perf_counter()
+    st = cold.solve()
+    t_cold = time.perf_counter() - t0
+    rows = [{"nu": 0.0, "iters": st["iters"], "seconds": t_cold, "state": st["state_name"]}]
+    for nu in (0.05, 0.1, 0.2, 0.3):
+        for keep in (True, False):
+            warm, spent = warmstart.warm_started(make, inst, nu, seed=int(nu * 1000), keep_omega=keep)
+            t0 = time.perf_counter()
+            st = warm.solve()
+            rows.append({"nu": nu, "keep_omega": keep, "perturbed_iters": spent, "iters": st["iters"],
+                         "seconds": time.perf_counter() - t0, "state": st["state_name"],
+                         "saving": 1.0 - (time.perf_counter() - t0) / t_cold})
+            warm.close()
+    print(json.dumps({"workload": "warm start, n=1000 ring+chords out-degree 10, log utility, rel KKT 1e-4",
+                      "precision": args.precision, "rows": rows}), flush=True)
+
+
+def knn_bench(args):
+    """The paper's own workload (Section 3.1): q-nearest-neighbour bidirected geometric graphs,
+    log utility with log w ~ U[log .3, log 3], log c ~ U[log .5, log 5], stopped by the paper's
+    rule r^k < n m eps with eps = 0.01 / (n (n-1)).  Iteration counts sit beside Table 1's
+    (for different random instances of the same recipe)."""
+    import torch
+    from paper_2501_17996_amd import instances as I
+    from paper_2501_17996_amd import mcf
+
+    torch.cuda.set_device(0)
+    paper = {(100, 10): (1178, 490, 0.5), (200, 10): (2316, 690, 0.7), (300, 10): (3472, 840, 0.8),
+             (500, 10): (5738, 950, 1.1), (500, 20): (11176, 790, 1.4), (1000, 10): (11424, 7220, 19.5),
+             (1000, 20): (22286, 1040, 5.1)}
+    prec = mcf.MCF_FP32 if args.precision == "fp32" else mcf.MCF_FP64
+    rows = []
+    for (n, q), (pm, pit, pt) in paper.items():
+        for seed in range(args.seeds):
+            inst = I.knn_geometric(n, q, seed)
+            eps = 0.01 / (n * (n - 1))
+            S = mcf.Solver(inst, precision=prec, tol=eps, stop_rule=mcf.MCF_STOP_PAPER, check_every=10,
+                           max_iter=200000)
+            t0 = time.perf_counter()
+            st = S.solve()
+            dt = time.perf_counter() - t0
+            rows.append({"n": n, "q": q, "seed": seed, "m": inst.m, "iters": st["iters"], "seconds": dt,
+                         "state": st["state_name"], "rel_kkt": st["rel_kkt"],
+                         "paper_m": pm, "paper_iters": pit, "paper_gpu_s": pt})
+            S.close()
+            print(json.dumps(rows[-1]), flush=True)
+    print(json.dumps({"workload": "kNN geometric graphs, paper stop rule", "precision": args.precision,
+                      "rows": rows}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -164,6 +231,7 @@ def main():
     ap.add_argument("--single", type=int, default=50, help="serving workload: FP64 single-instance comparison size")
     ap.add_argument("--serve-budget-gb", type=float, default=16.0)
     ap.add_argument("--serve-max-iter", type=int, default=60000)
+    ap.add_argument("--seeds", type=int, default=1, help="knn workload: seeds per size")
     ap.add_argument("--adapt-until", type=int, default=None,
                     help="freeze omega from this iteration on (Section 2.4); default: never for the solve "
                          "workloads, 1000 for the serving stream")
@@ -172,6 +240,12 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         raise SystemExit(2)
 
+    if args.workload == "warmstart":
+        warmstart_bench(args)
+        return
+    if args.workload == "knn":
+        knn_bench(args)
+        return
     if args.workload == "serve":
         if args.adapt_until is None:
             args.adapt_until = 1000
