@@ -143,10 +143,10 @@ def serve_bench(args):
 
 
 def warmstart_bench(args):
-    """Section 3.1 warm start: for perturbation ratios nu, the perturbed problem is solved until
-    its iterate is feasible; the original problem then starts from that (F, Y, omega).  Reports
-    iterations and seconds of the original solve, cold and warm, on the config3-shaped
-    instance with n=1000 (the paper's warm-start study uses n=1000, q=10)."""
+    """Section 3.1 warm start: the perturbed problem (weights (1 +/- nu) w) is solved until its
+    iterate is feasible; the original problem then starts from that (F, Y, omega).  Reports
+    iterations of the original solve, cold and warm, for several tolerances: how much a warm
+    start saves depends on how far past first feasibility the stopping rule lies."""
     import torch
     from paper_2501_17996_amd import instances as I
     from paper_2501_17996_amd import mcf, warmstart
@@ -154,33 +154,33 @@ def warmstart_bench(args):
     torch.cuda.set_device(0)
     inst = I.ring_instance(1000, 10, seed=11)
     prec = mcf.MCF_FP32 if args.precision == "fp32" else mcf.MCF_FP64
-
-    def make(i):
-        return mcf.Solver(i, precision=prec, tol=1e-4, check_every=10, max_iter=200000)
-
-    cold = make(inst)
-    t0 = time.perf_counter()
-    st = cold.solve()
-    t_cold = time.perf_counter() - t0
-    rows = [{"nu": 0.0, "iters": st["iters"], "seconds": t_cold, "state": st["state_name"]}]
-    for nu in (0.05, 0.1, 0.2, 0.3):
-        for keep in (True, False):
-            warm, spent = warmstart.warm_started(make, inst, nu, seed=int(nu * 1000), keep_omega=keep)
-            t0 = time.perf_counter()
-            st = warm.solve()
-            rows.append({"nu": nu, "keep_omega": keep, "perturbed_iters": spent, "iters": st["iters"],
-                         "seconds": time.perf_counter() - t0, "state": st["state_name"],
-                         "saving": 1.0 - (time.perf_counter() - t0) / t_cold})
-            warm.close()
-    print(json.dumps({"workload": "warm start, n=1000 ring+chords out-degree 10, log utility, rel KKT 1e-4",
+    rows = []
+    for tol in (1e-2, 1e-3, 1e-4):
+        def make(i, tol=tol):
+            return mcf.Solver(i, precision=prec, tol=tol, check_every=10, max_iter=200000)
+        cold = make(inst).solve()
+        rows.append({"tol": tol, "nu": 0.0, "iters": cold["iters"], "state": cold["state_name"]})
+        for nu in (0.1, 0.3):
+            for keep in (True, False):
+                warm, spent = warmstart.warm_started(make, inst, nu, seed=int(nu * 1000), keep_omega=keep)
+                st = warm.solve()
+                rows.append({"tol": tol, "nu": nu, "keep_omega": keep, "perturbed_iters": spent,
+                             "iters": st["iters"], "state": st["state_name"],
+                             "saving": 1.0 - st["iters"] / max(1, cold["iters"])})
+                warm.close()
+                print(json.dumps(rows[-1]), flush=True)
+    print(json.dumps({"workload": "warm start, n=1000 ring+chords out-degree 10, log utility",
                       "precision": args.precision, "rows": rows}), flush=True)
 
 
 def knn_bench(args):
     """The paper's own workload (Section 3.1): q-nearest-neighbour bidirected geometric graphs,
-    log utility with log w ~ U[log .3, log 3], log c ~ U[log .5, log 5], stopped by the paper's
-    rule r^k < n m eps with eps = 0.01 / (n (n-1)).  Iteration counts sit beside Table 1's
-    (for different random instances of the same recipe)."""
+    log utility with log w ~ U[log .3, log 3], log c ~ U[log .5, log 5].  Each instance runs
+    for the iteration count Table 1 reports for its size; at that point the relative duality
+    gap (p - d)/(1 + |p| + |d|) bounds the suboptimality of the utility, which the paper
+    states as 0.1% to 1% against an interior-point solver.  Also reported: the paper's
+    residual r^k / (n m) against its threshold eps = 0.01 / (n (n-1)), rel_kkt, and the time
+    per iteration beside the paper's H100 time per iteration (context only)."""
     import torch
     from paper_2501_17996_amd import instances as I
     from paper_2501_17996_amd import mcf
@@ -198,14 +198,15 @@ def knn_bench(args):
             S = mcf.Solver(inst, precision=prec, tol=eps, stop_rule=mcf.MCF_STOP_PAPER, check_every=10,
                            max_iter=200000)
             t0 = time.perf_counter()
-            st = S.solve()
+            st = S.run(pit)
             dt = time.perf_counter() - t0
             rows.append({"n": n, "q": q, "seed": seed, "m": inst.m, "iters": st["iters"], "seconds": dt,
-                         "state": st["state_name"], "rel_kkt": st["rel_kkt"],
-                         "paper_m": pm, "paper_iters": pit, "paper_gpu_s": pt})
+                         "ms_per_iter": dt / pit * 1e3, "rel_gap": st["rel_gap"], "rel_kkt": st["rel_kkt"],
+                         "r_paper": st["r_paper"], "eps": eps, "infeasible_frac": st["infeasible_frac"],
+                         "paper_m": pm, "paper_iters": pit, "paper_gpu_ms_per_iter": pt / pit * 1e3})
             S.close()
             print(json.dumps(rows[-1]), flush=True)
-    print(json.dumps({"workload": "kNN geometric graphs, paper stop rule", "precision": args.precision,
+    print(json.dumps({"workload": "kNN geometric graphs at Table 1 iteration counts", "precision": args.precision,
                       "rows": rows}), flush=True)
 
 
