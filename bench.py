@@ -14,6 +14,7 @@ a bounded sample of the same workload.
 """
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -175,12 +176,14 @@ def warmstart_bench(args):
 
 def knn_bench(args):
     """The paper's own workload (Section 3.1): q-nearest-neighbour bidirected geometric graphs,
-    log utility with log w ~ U[log .3, log 3], log c ~ U[log .5, log 5].  Each instance runs
-    for the iteration count Table 1 reports for its size; at that point the relative duality
-    gap (p - d)/(1 + |p| + |d|) bounds the suboptimality of the utility, which the paper
-    states as 0.1% to 1% against an interior-point solver.  Also reported: the paper's
-    residual r^k / (n m) against its threshold eps = 0.01 / (n (n-1)), rel_kkt, and the time
-    per iteration beside the paper's H100 time per iteration (context only)."""
+    log utility with log w ~ U[log .3, log 3], log c ~ U[log .5, log 5].  Section 3.1 states the
+    accuracy of its solutions as a normalized (per pair) utility within about 0.01 of the
+    optimum.  Here each instance runs in blocks of 10 iterations until the certified per-pair gap
+    (p - d) / (n (n-1)) is at most 0.01 (p - d bounds the suboptimality of -U, since d is the dual
+    function of (e-L) at a feasible dual), and reports that iteration count beside Table 1's, with
+    the first feasible iteration, the first with relative gap <= 1e-3, the first within 0.01 per
+    pair of the optimum p* of a long FP64 solve (the paper's own measure, against an interior-point
+    optimum), and the paper's residual r^k / (n m) against its threshold 0.01 / (n (n-1))."""
     import torch
     from paper_2501_17996_amd import instances as I
     from paper_2501_17996_amd import mcf
@@ -190,24 +193,54 @@ def knn_bench(args):
              (500, 10): (5738, 950, 1.1), (500, 20): (11176, 790, 1.4), (1000, 10): (11424, 7220, 19.5),
              (1000, 20): (22286, 1040, 5.1)}
     prec = mcf.MCF_FP32 if args.precision == "fp32" else mcf.MCF_FP64
+    limit = args.iters if args.iters > 0 else 20000
     rows = []
     for (n, q), (pm, pit, pt) in paper.items():
         for seed in range(args.seeds):
             inst = I.knn_geometric(n, q, seed)
             eps = 0.01 / (n * (n - 1))
             S = mcf.Solver(inst, precision=prec, tol=eps, stop_rule=mcf.MCF_STOP_PAPER, check_every=10,
-                           max_iter=200000)
+                           max_iter=limit)
+            first = {"feasible": None, "pair_gap_0.01": None, "rel_gap_1e-3": None, "paper_rule": None}
+            hist = []
             t0 = time.perf_counter()
-            st = S.run(pit)
-            dt = time.perf_counter() - t0
-            rows.append({"n": n, "q": q, "seed": seed, "m": inst.m, "iters": st["iters"], "seconds": dt,
-                         "ms_per_iter": dt / pit * 1e3, "rel_gap": st["rel_gap"], "rel_kkt": st["rel_kkt"],
-                         "r_paper": st["r_paper"], "eps": eps, "infeasible_frac": st["infeasible_frac"],
-                         "paper_m": pm, "paper_iters": pit, "paper_gpu_ms_per_iter": pt / pit * 1e3})
+            best_r = math.inf
+            while True:
+                st = S.run(10)
+                k, el = st["iters"], time.perf_counter() - t0
+                gap = st["primal_obj"] - st["dual_obj"]
+                best_r = min(best_r, st["r_paper"])
+                hist.append((k, el, st["primal_obj"]))
+                hits = {"feasible": st["infeasible_frac"] == 0.0,
+                        "pair_gap_0.01": math.isfinite(gap) and gap <= 0.01 * n * (n - 1),
+                        "rel_gap_1e-3": st["rel_gap"] <= 1e-3,
+                        "paper_rule": st["r_paper"] < eps}
+                for key, hit in hits.items():
+                    if hit and first[key] is None:
+                        first[key] = (k, el)
+                if first["pair_gap_0.01"] is not None or k >= limit or st["state_name"] != "running":
+                    break
+            per_it = el / max(1, k)
             S.close()
+            # the optimum p* from a long FP64 solve; p* - d* bounds its own error
+            R = mcf.Solver(inst, precision=mcf.MCF_FP64, tol=1e-6, check_every=100, max_iter=args.ref_iters)
+            rst = R.solve()
+            R.close()
+            p_star, d_star = rst["primal_obj"], rst["dual_obj"]
+            within = next(((k_, el_) for k_, el_, p_ in hist if math.isfinite(p_) and p_ - p_star <= 0.01 * n * (n - 1)),
+                          None)
+            rows.append({"n": n, "q": q, "seed": seed, "m": inst.m,
+                         **{f"iters_{key}": (v[0] if v else None) for key, v in first.items()},
+                         "iters_within_0.01_of_opt": within[0] if within else None,
+                         "seconds_within_0.01_of_opt": within[1] if within else None,
+                         "seconds_pair_gap_0.01": first["pair_gap_0.01"][1] if first["pair_gap_0.01"] else None,
+                         "ms_per_iter": per_it * 1e3, "min_r_over_nm": best_r, "eps": eps,
+                         "opt_per_pair": p_star / (n * (n - 1)), "opt_gap_per_pair": (p_star - d_star) / (n * (n - 1)),
+                         "opt_iters": rst["iters"], "opt_state": rst["state_name"],
+                         "paper_m": pm, "paper_iters": pit, "paper_seconds": pt})
             print(json.dumps(rows[-1]), flush=True)
-    print(json.dumps({"workload": "kNN geometric graphs at Table 1 iteration counts", "precision": args.precision,
-                      "rows": rows}), flush=True)
+    print(json.dumps({"workload": "kNN geometric graphs (Section 3.1 recipe) to the paper's stated accuracy",
+                      "precision": args.precision, "rows": rows}), flush=True)
 
 
 def main():
@@ -233,6 +266,7 @@ def main():
     ap.add_argument("--serve-budget-gb", type=float, default=16.0)
     ap.add_argument("--serve-max-iter", type=int, default=60000)
     ap.add_argument("--seeds", type=int, default=1, help="knn workload: seeds per size")
+    ap.add_argument("--ref-iters", type=int, default=60000, help="knn workload: iteration cap of the FP64 optimum")
     ap.add_argument("--adapt-until", type=int, default=None,
                     help="freeze omega from this iteration on (Section 2.4); default: never for the solve "
                          "workloads, 1000 for the serving stream")
