@@ -54,22 +54,17 @@ def workload(name: str):
 
 
 def alg_bytes(n: int, m: int, s: int, fused: bool, check: bool) -> float:
-    """Algorithmic bytes of one launch of the dominant kernel.
+    """Algorithmic bytes of one timed unit: one whole PDHG iteration, the single fused launch
+    or the edge and node launches of the two-phase organisation.
 
-    Fused iteration (one launch = one whole PDHG iteration): the per-iteration model
-    s (4 n m + 3 n^2) -- F read and written, Fbar written and read, Y read and written,
-    W read -- even though the fused launch never stores Fbar.
-    Two-phase edge launch: its share of that model, F read, F and Fbar written and each
-    Y column read once, s (3 n m + n^2).
-    A check launch also writes Fhat and D (2 s n m) and, when fused, T and U' (16 n^2)."""
-    if fused:
-        b = s * (4.0 * n * m + 3.0 * n * n)
-        if check:
-            b += 2.0 * s * n * m + 16.0 * n * n
-    else:
-        b = s * (3.0 * n * m + n * n)
-        if check:
-            b += 2.0 * s * n * m
+    The per-iteration model s (4 n m + 3 n^2): F read and written, Fbar written and read,
+    Y read and written, W read.  Neither organisation stores Fbar (the fused one recomputes
+    the projection at both end nodes, the two-phase one carries P = F A^T), but both are
+    credited with the model's bytes, which is what a plain implementation of the iteration
+    moves.  A check iteration also writes Fhat and D (2 s n m) and T and U' (16 n^2)."""
+    b = s * (4.0 * n * m + 3.0 * n * n)
+    if check:
+        b += 2.0 * s * n * m + 16.0 * n * n
     return b
 
 
@@ -352,7 +347,7 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(args.workload) if args.kernel_mode == 0 else None,
                      "alg_bytes_per_launch": alg / max(1, launches),
-                     "kernel": "fused iteration" if fused else "edge phase",
+                     "kernel": "fused iteration" if fused else "edge + node phases (one iteration)",
                      "avg_launch_us": edge_ms * 1e3 / max(1, launches),
                      "launches": launches},
     }

@@ -32,7 +32,8 @@ struct Consts {
     int nblk_node;         // node-phase blocks (partials per quantity)
     int node_block;        // threads per node-phase block (64 or 256)
     int fused;             // 1: node-centric single-launch iteration (n <= FUSED_MAX_N)
-    int nep, nnp;          // partials per edge quantity (dF, e, sup) and per node quantity
+    int nep, nnp;          // partials per edge quantity (dF, e, sup; one per tail node) and per node quantity
+    int nrp;               // partials of the residual pass (a, b; one per RES_EDGES edges)
 };
 
 // Algorithm 2.1 step 3 adapts omega at iterations k that are multiples of k_adapt (k = 0
@@ -44,6 +45,10 @@ __host__ __device__ inline bool adapts_at(const Consts &c, long long k)
 
 // Largest n served by the node-centric fused iteration (one wave per edge column).
 constexpr int FUSED_MAX_N = 512;
+// Incidence entries of one node staged in LDS at a time by the fused iteration.
+constexpr int FUSED_INC_CHUNK = 256;
+// Edges (one wave each) per block of the residual pass.
+constexpr int RES_EDGES = 16;
 
 // Offsets (in doubles) of the partial-sum segments.
 struct PartLayout {
@@ -54,9 +59,12 @@ struct PartLayout {
 
 // Device buffers of one instance.  In fused mode F, Y and mu ping-pong with F2, Y2,
 // mu2: iteration k reads the buffers of parity (k + parity offset) & 1 and writes the others.
+// The two-phase iteration keeps P = F A^T of the current F (n x n, like Y) and a staging
+// column per node, Sout[:, t] = sum of F over the edges leaving t, written by the edge phase.
 template <typename T>
 struct Bufs {
-    T *F, *Fbar, *Fhat, *D, *Y, *W;
+    T *F, *Fhat, *D, *Y, *W;
+    T *P, *Sout;
     T *F2, *Y2;
     double *mu2;
     double *That, *Up;
@@ -71,9 +79,9 @@ struct Bufs {
     DevScalars *sc;
 };
 
-// Per-edge launch shape of the two-phase edge kernel: `wpe` waves (of 64 lanes) per edge
-// column and `ept` 16-byte vectors per lane.  With wpe == 1 a 256-thread block carries 4
-// edges, one per wave.
+// Launch shape of the two-phase edge kernel: `wpe` waves (of 64 lanes) per tail node, which
+// project its out-edge columns one after another, and `ept` 16-byte vectors per lane.  With
+// wpe == 1 a 256-thread block carries 4 tail nodes, one per wave.
 struct EdgeShape {
     int wpe, ept;
 };
@@ -101,6 +109,9 @@ hipError_t launch_control(const Consts &c, const Bufs<T> &b, const PartLayout &p
                           long long k_after, hipStream_t st);
 template <typename T>
 hipError_t launch_poison(const Bufs<T> &b, int which, long long offset, hipStream_t st);
+// Two-phase iteration: P = F A^T recomputed from the current F (after F is set from outside).
+template <typename T>
+hipError_t launch_p_from_f(const Consts &c, const Bufs<T> &b, hipStream_t st);
 
 int node_block_for(int n);
 

@@ -1,13 +1,17 @@
 // libmcf device kernels for gfx950 (CDNA4, wave64).
 //
 // One PDHG iteration of Algorithm 2.1 (eq. (e-pdhg-step)) is two launches:
-//   edge phase : per edge column l (destination-major, contiguous n-vector):
-//                q = F[:,l] + alpha (Y[:,head] - Y[:,tail]); Fhat = (q - mu)_+ (the
-//                projection of Section 2.3, mu from an exact active-set search);
-//                Fbar = 2 Fhat - F; F <- rho Fhat + (1 - rho) F.
-//   node phase : per node column j: V = Fbar A^T as a deterministic gather over the
-//                in-edge and out-edge lists; Yhat = prox(Y - beta V) off the diagonal,
-//                0 on it (Section 2.3); Y <- rho Yhat + (1 - rho) Y.
+//   edge phase : per tail node t, for each edge column l leaving t (destination-major,
+//                contiguous n-vector): q = F[:,l] + alpha (Y[:,head] - Y[:,tail]);
+//                Fhat = (q - mu)_+ (the projection of Section 2.3, mu from an exact
+//                active-set search); F <- rho Fhat + (1 - rho) F; the new columns of
+//                the edges leaving t are summed into Sout[:,t].
+//   node phase : per node column j: P' = F A^T of the new F, from a gather over the
+//                in-edge list minus Sout[:,j].  Since Fbar = 2 Fhat - F_old and
+//                F_new = rho Fhat + (1 - rho) F_old, Fbar = (2/rho) F_new - ((2-rho)/rho) F_old,
+//                so V = Fbar A^T = (2/rho) P' - ((2-rho)/rho) P with P = F_old A^T kept from
+//                the previous iteration: Fbar is never stored.  Yhat = prox(Y - beta V) off
+//                the diagonal, 0 on it (Section 2.3); Y <- rho Yhat + (1 - rho) Y; P <- P'.
 // Iterations that adapt the primal weight (k a multiple of k_adapt) or check the
 // residual also write FP64 partials of ||dF||^2 and ||dY||^2 and end in a control
 // launch: FP64 fixed-order reduction, (e-primal_weight), the stop flag.  On check
@@ -244,6 +248,7 @@ __global__ void init_kernel(Consts c, Bufs<T> b, double omega0)
         // Section 2.5 initialization: Y^0 = I - 1 1^T (0 on the diagonal, -1 off it); padding stays 0.
         b.Y[x] = (i < c.n && i != j) ? T(-1) : T(0);
         b.That[x] = 0.0;
+        if (!c.fused) b.P[x] = T(0);  // P = F A^T of F = 0
     }
     for (long long x = t0; x < c.m; x += stride) b.mu[x] = 0.0;
     if (t0 == 0) {
@@ -287,14 +292,38 @@ __device__ __forceinline__ void vstore(T *p, const T (&x)[Vec<T>::N])
     *reinterpret_cast<typename Vec<T>::type *>(p) = v;
 }
 
+// Streaming (non-temporal) forms for data touched once per iteration, so that the lines that
+// are reused (a tail's Y column, read once per out-edge) keep their place in the L2.
+template <typename T> struct NtVec;
+template <> struct NtVec<float> { typedef float type __attribute__((ext_vector_type(4))); };
+template <> struct NtVec<double> { typedef double type __attribute__((ext_vector_type(2))); };
+
+template <typename T>
+__device__ __forceinline__ void vload_nt(const T *p, T (&x)[Vec<T>::N])
+{
+    const typename NtVec<T>::type v = __builtin_nontemporal_load(reinterpret_cast<const typename NtVec<T>::type *>(p));
+#pragma unroll
+    for (int u = 0; u < Vec<T>::N; ++u) x[u] = v[u];
+}
+
+template <typename T>
+__device__ __forceinline__ void vstore_nt(T *p, const T (&x)[Vec<T>::N])
+{
+    typename NtVec<T>::type v;
+#pragma unroll
+    for (int u = 0; u < Vec<T>::N; ++u) v[u] = x[u];
+    __builtin_nontemporal_store(v, reinterpret_cast<typename NtVec<T>::type *>(p));
+}
+
 // The largest value of type T that is <= x: for q of type T, q > x exactly when q > below(x).
 __device__ __forceinline__ float below(double x, float) { return __double2float_rd(x); }
 __device__ __forceinline__ double below(double x, double) { return x; }
 
-// WPE waves per edge column (WPE == 1: a 256-thread block carries 4 edges, one per wave),
-// each lane holding NV 16-byte vectors of F[:,l] and q.  Vector v of lane t covers entries
-// (v * 64 * WPE + t) * VEC .. + VEC - 1; a vector that starts below n is loaded whole: the
-// padding rows n .. ld-1 of F and Y are zero, so their q is 0 and they never enter a support.
+// WPE waves per tail node t (WPE == 1: a 256-thread block carries 4 tail nodes, one per
+// wave); they project the edges leaving t one after another, each lane holding NV 16-byte
+// vectors of F[:,l] and q.  Vector v of lane x covers entries (v * 64 * WPE + x) * VEC ..
+// + VEC - 1; a vector that starts below n is loaded whole: the padding rows n .. ld-1 of F
+// and Y are zero, so their q is 0 and they never enter a support.
 // mu (Section 2.3, Section 2.6): mu = 0 if sum (q)_+ <= c; otherwise the support S and
 // mu = (sum_S q - c)/|S| satisfy S = {q > mu}.  Any mu' with S' = {q > mu'} nonempty
 // gives the lower bound (sum_{S'} q - c)/|S'| <= mu (the linear function it zeroes lies
@@ -303,150 +332,178 @@ __device__ __forceinline__ double below(double x, double) { return x; }
 // stops exactly when |S| stops shrinking.  The search starts from the larger of the
 // bounds given by S' = {q > 0} and S' = {q > mu of the previous iteration}, so a
 // column whose support did not move needs two block sums instead of five or six.
+// The new columns of the edges leaving t are added, in edge order and in the iterate type,
+// into Sout[:,t], the out-edge half of P' = F A^T.  (In FP32 that sum of the few columns
+// leaving a node carries rounding of the same order as the FP32 columns themselves.)
 template <typename T, int WPE, int NV, bool CHECK, bool PARTIAL>
 __global__ __launch_bounds__(WPE == 1 ? 256 : 64 * WPE) void edge_kernel(Consts c, Bufs<T> b, PartLayout pl)
 {
     constexpr int VEC = Vec<T>::N;
-    constexpr int LANES = 64 * WPE;  // threads per edge column
+    constexpr int LANES = 64 * WPE;  // threads per tail node
+    constexpr int NT = WPE == 1 ? 256 : 64 * WPE;
     __shared__ double lds[2 * WPE];
+    // the out-edge sums live in LDS, one 16-byte vector per (vector slot, thread): in
+    // registers they would cost the occupancy that keeps enough loads in flight
+    __shared__ typename Vec<T>::type sol[NV * NT];
     if (b.sc->stop) return;
-    const int items = WPE == 1 ? (c.m + 3) / 4 : c.m;
+    const int items = WPE == 1 ? (c.n + 3) / 4 : c.n;
     const int blk = xcd_item(blockIdx.x, items);
     if (blk >= items) return;
-    const int e = WPE == 1 ? blk * 4 + (int)(threadIdx.x >> 6) : blk;
-    if (e >= c.m) return;  // whole waves only (WPE == 1): no block barrier follows
+    const int tn = WPE == 1 ? blk * 4 + (int)(threadIdx.x >> 6) : blk;
+    if (tn >= c.n) return;  // whole waves only (WPE == 1): no block barrier follows
     const int t = WPE == 1 ? (int)(threadIdx.x & 63) : (int)threadIdx.x;
     const int n = c.n;
     const long long ld = c.ld;
     const T ta = (T)b.sc->alpha;
-    const T *yh = b.Y + (long long)b.head[e] * ld;
-    const T *yt = b.Y + (long long)b.tail[e] * ld;
-    T *f = b.F + (long long)e * ld;
-    const double cap = b.cap[e];
-    const double mu0 = b.mu[e];
-    T fo[NV][VEC], q[NV][VEC];
+    const T *yt = b.Y + (long long)tn * ld;
+    const double rho = c.rho, omr = 1.0 - c.rho;
+    typename Vec<T>::type *so = sol + threadIdx.x;  // slot v at so[v * NT]
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-        const int i = (v * LANES + t) * VEC;
-        if (i < n) {
-            T a[VEC], bh[VEC], bt[VEC];
-            vload(f + i, a);
-            vload(yh + i, bh);
-            vload(yt + i, bt);
-#pragma unroll
-            for (int u = 0; u < VEC; ++u) {
-                fo[v][u] = a[u];
-                q[v][u] = a[u] + ta * (bh[u] - bt[u]);
-            }
-        } else {
-#pragma unroll
-            for (int u = 0; u < VEC; ++u) {
-                fo[v][u] = T(0);
-                q[v][u] = T(0);
-            }
-        }
+        const T z[VEC] = {};
+        vstore(reinterpret_cast<T *>(so + v * NT), z);
     }
-    // Sums over a support {q > thr}: each 16-byte vector is first added in the iterate type
-    // (in a fixed order), then in FP64.  Converting per vector rather than per entry keeps the
-    // compiler from holding an FP64 copy of every q across the passes.
-    auto support_sum = [&](T thr, double &s, int &cnt) {
+    const int e0 = b.out_off[tn], e1 = b.out_off[tn + 1];
+    double dF_t = 0.0, e_t = 0.0, sup_t = 0.0;  // this tail's partials, edge by edge in order
+    for (int e = e0; e < e1; ++e) {
+        // e is uniform within the wave, so is its head: keep the column address scalar
+        const T *yh = b.Y + (long long)__builtin_amdgcn_readfirstlane(b.head[e]) * ld;
+        T *f = b.F + (long long)e * ld;
+        const double cap = b.cap[e];
+        const double mu0 = b.mu[e];
+        // All 3 NV loads are issued before any is used: a vector past n reads the column's
+        // first vector instead (always in bounds) and is then replaced by zeros.
+        T fo[NV][VEC], q[NV][VEC], bh[NV][VEC], bt[NV][VEC];
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-            T part = T(0);
-#pragma unroll
-            for (int u = 0; u < VEC; ++u)
-                if (q[v][u] > thr) {
-                    part += q[v][u];
-                    ++cnt;
-                }
-            s += (double)part;
+            const int i = (v * LANES + t) * VEC;
+            const int ic = i < n ? i : 0;
+            vload_nt(f + ic, fo[v]);
+            vload_nt(yh + ic, bh[v]);
+            vload(yt + ic, bt[v]);
         }
-    };
-    const T thr0 = below(mu0, T(0));
-    double sp = 0.0, sw = 0.0;
-    int cp = 0, cw = 0;
-    support_sum(T(0), sp, cp);
-    support_sum(thr0, sw, cw);
-    group_sum<WPE>(sp, cp, lds);
-    group_sum<WPE>(sw, cw, lds);
-    double mu = 0.0;
-    if (sp > cap) {
-        mu = (sp - cap) / cp;
-        int prev = cp;  // mu came from S' = {q > 0}, a superset of {q > mu}
-        if (cw > 0) {
-            const double mw = (sw - cap) / cw;
-            if (mw > mu) {
-                mu = mw;
-                prev = mw >= mu0 ? cw : 0x7fffffff;  // {q > mu0} contains {q > mw} only if mw >= mu0
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const bool ok = (v * LANES + t) * VEC < n;
+#pragma unroll
+            for (int u = 0; u < VEC; ++u) {
+                q[v][u] = ok ? fo[v][u] + ta * (bh[v][u] - bt[v][u]) : T(0);
+                fo[v][u] = ok ? fo[v][u] : T(0);
             }
         }
-        for (int pass = 0; pass <= n; ++pass) {
-            double s = 0.0;
-            int cnt = 0;
-            support_sum(below(mu, T(0)), s, cnt);
-            group_sum<WPE>(s, cnt, lds);
-            if (cnt >= prev) break;
-            mu = (s - cap) / cnt;
-            prev = cnt;
+        // Sums over a support {q > thr}: each 16-byte vector is first added in the iterate
+        // type (in a fixed order), then in FP64.  Converting per vector rather than per entry
+        // keeps the compiler from holding an FP64 copy of every q across the passes.
+        auto support_sum = [&](T thr, double &s, int &cnt) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                T part = T(0);
+#pragma unroll
+                for (int u = 0; u < VEC; ++u)
+                    if (q[v][u] > thr) {
+                        part += q[v][u];
+                        ++cnt;
+                    }
+                s += (double)part;
+            }
+        };
+        const T thr0 = below(mu0, T(0));
+        double sp = 0.0, sw = 0.0;
+        int cp = 0, cw = 0;
+        support_sum(T(0), sp, cp);
+        support_sum(thr0, sw, cw);
+        group_sum<WPE>(sp, cp, lds);
+        group_sum<WPE>(sw, cw, lds);
+        double mu = 0.0;
+        if (sp > cap) {
+            mu = (sp - cap) / cp;
+            int prev = cp;  // mu came from S' = {q > 0}, a superset of {q > mu}
+            if (cw > 0) {
+                const double mw = (sw - cap) / cw;
+                if (mw > mu) {
+                    mu = mw;
+                    prev = mw >= mu0 ? cw : 0x7fffffff;  // {q > mu0} contains {q > mw} only if mw >= mu0
+                }
+            }
+            for (int pass = 0; pass <= n; ++pass) {
+                double s = 0.0;
+                int cnt = 0;
+                support_sum(below(mu, T(0)), s, cnt);
+                group_sum<WPE>(s, cnt, lds);
+                if (cnt >= prev) break;
+                mu = (s - cap) / cnt;
+                prev = cnt;
+            }
+        }
+        double dsum = 0.0, esum = 0.0, gmax = -INFINITY;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const int i = (v * LANES + t) * VEC;
+            if (i < n) {
+                T fn[VEC], fhv[VEC], dv[VEC], sv[VEC];
+                vload(reinterpret_cast<const T *>(so + v * NT), sv);
+#pragma unroll
+                for (int u = 0; u < VEC; ++u) {
+                    // widen F here, not at its load: an FP64 copy of every entry held across
+                    // the multiplier search would double the registers the column takes
+                    T fov = fo[v][u];
+                    asm volatile("" : "+v"(fov));
+                    const double fod = (double)fov;
+                    const double fh = fmax((double)q[v][u] - mu, 0.0);
+                    fn[u] = (T)(rho * fh + omr * fod);
+                    sv[u] += fn[u];
+                    if (PARTIAL) {
+                        const double d = (double)fn[u] - fod;
+                        dsum += d * d;
+                    }
+                    if (CHECK) {
+                        fhv[u] = (T)fh;
+                        dv[u] = (T)(fh - (double)q[v][u]);
+                        esum += (double)dv[u] * (double)dv[u];
+                    }
+                }
+                vstore_nt(f + i, fn);
+                vstore(reinterpret_cast<T *>(so + v * NT), sv);
+                if (CHECK) {
+                    vstore_nt(b.Fhat + (long long)e * ld + i, fhv);
+                    vstore_nt(b.D + (long long)e * ld + i, dv);
+                    T bh[VEC], bt[VEC];
+                    vload(yh + i, bh);
+                    vload(yt + i, bt);
+#pragma unroll
+                    for (int u = 0; u < VEC; ++u)
+                        if (i + u < n) gmax = fmax(gmax, (double)(bh[u] - bt[u]));
+                }
+            }
+        }
+        if (PARTIAL) group_sum<WPE>(dsum, esum, lds);
+        if (CHECK) gmax = group_max<WPE>(gmax, lds);
+        if (t == 0) b.mu[e] = mu;
+        dF_t += dsum;
+        e_t += esum;
+        if (CHECK) sup_t += cap * fmax(gmax, 0.0);  // c_l (max_i (Y A)_il)_+
+    }
+    if (t == 0) {
+        if (PARTIAL) b.part[pl.dF + tn] = dF_t;
+        if (CHECK) {
+            b.part[pl.e + tn] = e_t;
+            b.part[pl.sup + tn] = sup_t;
         }
     }
-    T *fb = b.Fbar + (long long)e * ld;
-    const double rho = c.rho, omr = 1.0 - c.rho;
-    double dsum = 0.0, esum = 0.0, gmax = -INFINITY;
+    T *sout = b.Sout + (long long)tn * ld;
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
         const int i = (v * LANES + t) * VEC;
-        if (i < n) {
-            T fn[VEC], fbv[VEC], fhv[VEC], dv[VEC];
-#pragma unroll
-            for (int u = 0; u < VEC; ++u) {
-                const double fod = (double)fo[v][u];
-                const double fh = fmax((double)q[v][u] - mu, 0.0);
-                fn[u] = (T)(rho * fh + omr * fod);
-                fbv[u] = (T)(2.0 * fh - fod);
-                if (PARTIAL) {
-                    const double d = (double)fn[u] - fod;
-                    dsum += d * d;
-                }
-                if (CHECK) {
-                    fhv[u] = (T)fh;
-                    dv[u] = (T)(fh - (double)q[v][u]);
-                    esum += (double)dv[u] * (double)dv[u];
-                }
-            }
-            vstore(f + i, fn);
-            vstore(fb + i, fbv);
-            if (CHECK) {
-                vstore(b.Fhat + (long long)e * ld + i, fhv);
-                vstore(b.D + (long long)e * ld + i, dv);
-                T bh[VEC], bt[VEC];
-                vload(yh + i, bh);
-                vload(yt + i, bt);
-#pragma unroll
-                for (int u = 0; u < VEC; ++u)
-                    if (i + u < n) gmax = fmax(gmax, (double)(bh[u] - bt[u]));
-            }
-        }
-    }
-    if (PARTIAL) group_sum<WPE>(dsum, esum, lds);
-    if (CHECK) gmax = group_max<WPE>(gmax, lds);
-    if (t == 0) {
-        b.mu[e] = mu;
-        if (PARTIAL) b.part[pl.dF + e] = dsum;
-        if (CHECK) {
-            b.part[pl.e + e] = esum;
-            b.part[pl.sup + e] = cap * fmax(gmax, 0.0);  // c_l (max_i (Y A)_il)_+
-        }
+        if (i < n) *reinterpret_cast<typename Vec<T>::type *>(sout + i) = so[v * NT];
     }
 }
 
 // -------------------------------------------------------------- node phase
-// Grid (ceil(n/NB), n): thread (x, j) owns entry i of node column j.
-// V_ij = sum_{l in in(j)} Fbar_il - sum_{l in out(j)} Fbar_il, accumulated in FP64 in CSR
-// order; loads are issued eight edges at a time, the additions stay in list order.
-template <typename T, int NB>
-__device__ __forceinline__ double gather_in_minus_out(const T *X, const int *in_edge, int i0, int i1, int o0, int o1,
-                                                     long long ld, int i)
+// Grid (ceil(n/NB), n): thread (x, j) owns entry i of node column j.  Gathers over the
+// CSR edge lists accumulate in FP64 in list order; loads are issued eight edges at a
+// time, the additions stay in list order.
+template <typename T>
+__device__ __forceinline__ double gather_in(const T *X, const int *in_edge, int i0, int i1, long long ld, int i)
 {
     double v = 0.0;
     int k = i0;
@@ -458,16 +515,31 @@ __device__ __forceinline__ double gather_in_minus_out(const T *X, const int *in_
         for (int u = 0; u < 8; ++u) v += (double)a[u];
     }
     for (; k < i1; ++k) v += (double)X[(long long)in_edge[k] * ld + i];
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ double gather_out(const T *X, int o0, int o1, long long ld, int i)
+{
+    double v = 0.0;
     int e = o0;
     for (; e + 8 <= o1; e += 8) {
         T a[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) a[u] = X[(long long)(e + u) * ld + i];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) v -= (double)a[u];
+        for (int u = 0; u < 8; ++u) v += (double)a[u];
     }
-    for (; e < o1; ++e) v -= (double)X[(long long)e * ld + i];
+    for (; e < o1; ++e) v += (double)X[(long long)e * ld + i];
     return v;
+}
+
+// (F A^T)_ij = sum_{l in in(j)} F_il - sum_{l in out(j)} F_il with the out-edge sum first
+// rounded to the iterate type, exactly as the edge phase stages it in Sout.
+template <typename T>
+__device__ __forceinline__ double p_entry(const T *X, const int *in_edge, int i0, int i1, T sout, long long ld, int i)
+{
+    return gather_in<T>(X, in_edge, i0, i1, ld, i) - (double)sout;
 }
 
 template <typename T, int NB, int UTIL, bool CHECK, bool PARTIAL>
@@ -483,9 +555,13 @@ __global__ __launch_bounds__(NB) void node_kernel(Consts c, Bufs<T> b, PartLayou
     const double beta = b.sc->beta, g = c.gamma;
     double dy2 = 0.0, p = 0.0, conj = 0.0, rnum = 0.0, rden = 0.0, nonpos = 0.0, yinf = 0.0;
     if (i < c.n) {
-        const int i0 = b.in_off[j], i1 = b.in_off[j + 1], o0 = b.out_off[j], o1 = b.out_off[j + 1];
-        const double v = gather_in_minus_out<T, NB>(b.Fbar, b.in_edge, i0, i1, o0, o1, ld, i);
+        const int i0 = b.in_off[j], i1 = b.in_off[j + 1];
         const long long x = (long long)j * ld + i;
+        // P' = F_new A^T; V = Fbar A^T = (2/rho) P' - ((2 - rho)/rho) P
+        const double pn = p_entry<T>(b.F, b.in_edge, i0, i1, b.Sout[x], ld, i);
+        const double po = (double)b.P[x];
+        b.P[x] = (T)pn;
+        const double v = (2.0 / c.rho) * pn - ((2.0 - c.rho) / c.rho) * po;
         const double y = (double)b.Y[x];
         const double w = (double)b.W[x];
         const double yhat = (i != j) ? prox_dual<UTIL>(y - beta * v, beta, w, g, c.c1) : 0.0;
@@ -497,7 +573,8 @@ __global__ __launch_bounds__(NB) void node_kernel(Consts c, Bufs<T> b, PartLayou
         }
         if (CHECK) {
             // T = -Fhat A^T, U' = u'(T), and the pieces of p, d and rel_primal (with Y^k = y).
-            const double t = -gather_in_minus_out<T, NB>(b.Fhat, b.in_edge, i0, i1, o0, o1, ld, i);
+            const int o0 = b.out_off[j], o1 = b.out_off[j + 1];
+            const double t = gather_out<T>(b.Fhat, o0, o1, ld, i) - gather_in<T>(b.Fhat, b.in_edge, i0, i1, ld, i);
             b.That[x] = t;
             double up = 0.0;
             if (i != j) {
@@ -541,6 +618,20 @@ __global__ __launch_bounds__(NB) void node_kernel(Consts c, Bufs<T> b, PartLayou
     }
 }
 
+// P = F A^T of the current F, with the out-edge sums formed in the iterate type and edge
+// order as the edge phase forms them, so that P is the one an uninterrupted run would hold.
+template <typename T, int NB>
+__global__ __launch_bounds__(NB) void p_from_f_kernel(Consts c, Bufs<T> b)
+{
+    const int j = blockIdx.y;
+    const int i = blockIdx.x * NB + threadIdx.x;
+    if (i >= c.n) return;
+    T so = T(0);
+    for (int e = b.out_off[j]; e < b.out_off[j + 1]; ++e) so += b.F[(long long)e * c.ld + i];
+    const long long x = (long long)j * c.ld + i;
+    b.P[x] = (T)p_entry<T>(b.F, b.in_edge, b.in_off[j], b.in_off[j + 1], so, c.ld, i);
+}
+
 // ----------------------------------------------------- fused node iteration
 // For n <= 64*EPT <= FUSED_MAX_N one PDHG iteration is a single launch: workgroup j
 // (four waves) recomputes, one wave per column, the projection of every edge incident
@@ -554,13 +645,18 @@ template <int EPT, bool CHECK>
 constexpr int fused_waves() { return (CHECK || EPT > 4) ? 8 : 16; }
 
 // The body of one fused iteration for node j, run by NWV waves.  `vsh` holds
-// (CHECK ? 2 : 1) * NWV * EPT * 64 doubles and `red` 2 * NWV doubles of LDS.
-template <typename T, int EPT, int UTIL, bool CHECK, bool PARTIAL, int NWV>
+// (CHECK ? 2 : 1) * NWV * EPT * 64 doubles, `red` 2 * NWV doubles and `incs`
+// FUSED_INC_CHUNK incidence entries of LDS.
+// Memory latency is what bounds this body, so: the node's incidence entries are staged in
+// LDS by the whole workgroup (one round trip instead of one per edge), every column load is
+// unconditional (entries past n read entry 0 of the column and are then discarded), and each
+// wave loads the columns of its next edge before it projects the current one.
+template <typename T, int EPT, int UTIL, bool CHECK, bool PARTIAL, int NWV, bool STOPCHK>
 __device__ __forceinline__ void fused_body(const Consts &c, const Bufs<T> &b, const PartLayout &pl, int parity, int j,
-                                           double *vsh, double *red)
+                                           double *vsh, double *red, int2 *incs)
 {
     constexpr int RPT = (64 * EPT + 64 * NWV - 1) / (64 * NWV);  // node-phase rows per thread
-    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int n = c.n;
     const long long ld = c.ld;
     const T *Fc = parity ? b.F2 : b.F;
@@ -571,41 +667,76 @@ __device__ __forceinline__ void fused_body(const Consts &c, const Bufs<T> &b, co
     double *mun = parity ? b.mu : b.mu2;
     const T ta = (T)b.sc->alpha;
     const double beta = b.sc->beta, g = c.gamma, rho = c.rho, omr = 1.0 - c.rho;
-    const int k0 = b.inc_off[j], deg = b.inc_off[j + 1] - k0;
+    const int k0 = b.inc_off[j], k1 = b.inc_off[j + 1], deg = k1 - k0;
     const T *yj = Yc + (long long)j * ld;
-    // node-phase operands, loaded before the edge loop so their latency overlaps it
-    double yrow[RPT], wrow[RPT];
+    // node-phase operands, loaded before the edge loop so their latency overlaps it (rows
+    // past n read row 0 and are never used)
+    T yrow[RPT], wrow[RPT];
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
         const int i = threadIdx.x + r * 64 * NWV;
-        yrow[r] = i < n ? (double)yj[i] : 0.0;
-        wrow[r] = i < n ? (double)b.W[(long long)j * ld + i] : 0.0;
+        const int ic = i < n ? i : 0;
+        yrow[r] = yj[ic];
+        wrow[r] = b.W[(long long)j * ld + ic];
     }
     // column j of Y, shared by every edge incident to j (its head or its tail column)
     T yjl[EPT];
 #pragma unroll
     for (int jj = 0; jj < EPT; ++jj) {
         const int i = lane + jj * 64;
-        yjl[jj] = i < n ? yj[i] : T(0);
+        yjl[jj] = yj[i < n ? i : 0];
     }
+    // the stop flag is read with the offsets, after the loads above are issued, so that no
+    // round trip to memory is spent on it alone
+    if (STOPCHK && (b.sc->stop | (k1 < k0))) return;
     double vacc[EPT], tacc[EPT];
 #pragma unroll
     for (int jj = 0; jj < EPT; ++jj) vacc[jj] = tacc[jj] = 0.0;
     double dsum = 0.0, esum = 0.0, supsum = 0.0;
-    for (int idx = wv; idx < deg; idx += NWV) {
-        const int2 ent = b.inc[k0 + idx];
-        const bool out = ent.y < 0;  // edge leaves j: j is its tail
+    // F[:,e] and Y[:,other end] of incidence entry x (in LDS), with the edge's c and mu
+    auto fetch = [&](int x, T (&fv)[EPT], T (&yv)[EPT], double &cap, double &mu0) {
+        const int2 ent = incs[x];
         const int e = ent.x, o = ent.y & 0x7fffffff;
-        const T *yo = Yc + (long long)o * ld;
         const T *f = Fc + (long long)e * ld;
-        const double cap = b.cap[e], mu0 = muc[e];
+        const T *yo = Yc + (long long)o * ld;
+#pragma unroll
+        for (int jj = 0; jj < EPT; ++jj) {
+            const int i = lane + jj * 64;
+            const int ic = i < n ? i : 0;
+            fv[jj] = f[ic];
+            yv[jj] = yo[ic];
+        }
+        cap = b.cap[e];
+        mu0 = muc[e];
+    };
+    // One chunk of incidence entries: staged in LDS, then projected wave by wave.  The first
+    // chunk (usually the only one) is a call of its own, outside any loop, so that the waits
+    // the compiler places at a loop head do not hold up the loads issued above.
+    auto chunk = [&](int base) {
+        const int cnt = min(FUSED_INC_CHUNK, deg - base);
+        if (base > 0) __syncthreads();  // the previous chunk is consumed
+        for (int x = threadIdx.x; x < cnt; x += 64 * NWV) incs[x] = b.inc[k0 + base + x];
+        __syncthreads();
+        T fa[EPT], ya[EPT];
+        double capa = 0.0, mu0a = 0.0;
+        if (wv < cnt) fetch(wv, fa, ya, capa, mu0a);
+    for (int idx = wv; idx < cnt; idx += NWV) {
+        // the next edge of this wave (the last one again when there is none: no branch, so
+        // the wait for the current edge's columns does not also wait for these loads)
+        T fnx[EPT], ynx[EPT];
+        double capn, mu0n;
+        fetch(min(idx + NWV, cnt - 1), fnx, ynx, capn, mu0n);
+        const int2 ent = incs[idx];
+        const bool out = ent.y < 0;  // edge leaves j: j is its tail
+        const int e = ent.x;
+        const double cap = capa, mu0 = mu0a;
         T fo[EPT], q[EPT];
 #pragma unroll
         for (int jj = 0; jj < EPT; ++jj) {
             const int i = lane + jj * 64;
             if (i < n) {
-                fo[jj] = f[i];
-                const T yv = yo[i];
+                fo[jj] = fa[jj];
+                const T yv = ya[jj];
                 q[jj] = fo[jj] + ta * (out ? yv - yjl[jj] : yjl[jj] - yv);  // Y[:,head] - Y[:,tail]
             } else {
                 fo[jj] = T(0);
@@ -669,7 +800,7 @@ __device__ __forceinline__ void fused_body(const Consts &c, const Bufs<T> &b, co
                         const T dd = (T)(fh - (double)q[jj]);
                         b.D[(long long)e * ld + i] = dd;
                         esum += (double)dd * (double)dd;
-                        gmax = fmax(gmax, (double)(yo[i] - yjl[jj]));  // (Y A)_il of the leaving edge
+                        gmax = fmax(gmax, (double)(ya[jj] - yjl[jj]));  // (Y A)_il of the leaving edge
                     }
                 }
             }
@@ -678,7 +809,17 @@ __device__ __forceinline__ void fused_body(const Consts &c, const Bufs<T> &b, co
             if (lane == 0) mun[e] = mu;
             if (CHECK) supsum += cap * fmax(wave_max(gmax), 0.0);  // c_l (max_i (Y A)_il)_+
         }
+#pragma unroll
+        for (int jj = 0; jj < EPT; ++jj) {
+            fa[jj] = fnx[jj];
+            ya[jj] = ynx[jj];
+        }
+        capa = capn;
+        mu0a = mu0n;
     }
+    };
+    chunk(0);
+    for (int base = FUSED_INC_CHUNK; base < deg; base += FUSED_INC_CHUNK) chunk(base);
 #pragma unroll
     for (int jj = 0; jj < EPT; ++jj) {
         vsh[(wv * EPT + jj) * 64 + lane] = vacc[jj];
@@ -698,7 +839,7 @@ __device__ __forceinline__ void fused_body(const Consts &c, const Bufs<T> &b, co
             if (CHECK) t += vsh[NWV * EPT * 64 + (w * EPT + jj) * 64 + L];
         }
         const long long x = (long long)j * ld + i;
-        const double y = yrow[r], w = wrow[r];
+        const double y = (double)yrow[r], w = (double)wrow[r];
         const double yhat = (i != j) ? prox_dual<UTIL>(y - beta * v, beta, w, g, c.c1) : 0.0;
         const T yn = (T)(rho * yhat + omr * y);
         Yn[x] = yn;
@@ -762,49 +903,84 @@ __global__ __launch_bounds__((64 * fused_waves<EPT, CHECK>())) void fused_kernel
     constexpr int NWV = fused_waves<EPT, CHECK>();
     extern __shared__ double vsh[];
     __shared__ double red[2 * NWV];
-    if (b.sc->stop) return;
-    fused_body<T, EPT, UTIL, CHECK, PARTIAL, NWV>(c, b, pl, parity, (int)blockIdx.x, vsh, red);
+    __shared__ int2 incs[FUSED_INC_CHUNK];
+    fused_body<T, EPT, UTIL, CHECK, PARTIAL, NWV, true>(c, b, pl, parity, (int)blockIdx.x, vsh, red, incs);
 }
 
 // ---------------------------------------------------------- residual pass
-// Per edge: G[:,l] = U'[:,head] - U'[:,tail]; partials ||G_l||^2 and <G_l, D_l>.
-// One wave per edge, four edges per 256-thread block.
+// Per edge: G[:,l] = U'[:,head] - U'[:,tail]; ||G_l||^2 and <G_l, D_l>.  One wave per edge,
+// RES_EDGES consecutive edges per block; the block adds its edges' values in edge order and
+// writes one partial per block.
 template <typename T>
-__device__ __forceinline__ void residual_body(const Consts &c, const Bufs<T> &b, const PartLayout &pl, int e)
+__device__ __forceinline__ void residual_edge(const Consts &c, const Bufs<T> &b, int e, double &a, double &bb)
 {
     const int lane = threadIdx.x & 63;
     const long long ld = c.ld;
-    const double *uh = b.Up + (long long)b.head[e] * ld;
-    const double *ut = b.Up + (long long)b.tail[e] * ld;
+    const double *uh = b.Up + (long long)__builtin_amdgcn_readfirstlane(b.head[e]) * ld;
+    const double *ut = b.Up + (long long)__builtin_amdgcn_readfirstlane(b.tail[e]) * ld;
     const T *d = b.D + (long long)e * ld;
-    double a = 0.0, bb = 0.0;
-    for (int i = lane; i < c.n; i += 64) {
-        const double gg = uh[i] - ut[i];
-        a += gg * gg;
-        bb += gg * (double)d[i];
+    a = 0.0;
+    bb = 0.0;
+    // four rows per lane and pass, loaded unconditionally (rows past n read row 0 and are
+    // discarded) so that the twelve loads of a pass are in flight together
+    for (int i0 = lane; i0 < c.n; i0 += 256) {
+        double h4[4], t4[4], d4[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int i = i0 + 64 * u, ic = i < c.n ? i : 0;
+            h4[u] = uh[ic];
+            t4[u] = ut[ic];
+            d4[u] = (double)d[ic];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (i0 + 64 * u < c.n) {
+                const double gg = h4[u] - t4[u];
+                a += gg * gg;
+                bb += gg * d4[u];
+            }
     }
     a = wave_sum(a);
     bb = wave_sum(bb);
-    if (lane == 0) {
-        b.part[pl.a + e] = a;
-        b.part[pl.b + e] = bb;
+}
+
+// Block `blk` of the residual pass (RES_EDGES waves); `lds` holds 2 * RES_EDGES doubles.
+template <typename T>
+__device__ __forceinline__ void residual_body(const Consts &c, const Bufs<T> &b, const PartLayout &pl, int blk,
+                                              double *lds)
+{
+    const int w = threadIdx.x >> 6, e = blk * RES_EDGES + w;
+    double a = 0.0, bb = 0.0;
+    if (e < c.m) residual_edge<T>(c, b, e, a, bb);
+    if ((threadIdx.x & 63) == 0) {
+        lds[w] = a;
+        lds[RES_EDGES + w] = bb;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double sa = 0.0, sb = 0.0;
+        for (int x = 0; x < RES_EDGES; ++x) {
+            sa += lds[x];
+            sb += lds[RES_EDGES + x];
+        }
+        b.part[pl.a + blk] = sa;
+        b.part[pl.b + blk] = sb;
     }
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void residual_kernel(Consts c, Bufs<T> b, PartLayout pl)
+__global__ __launch_bounds__(64 * RES_EDGES) void residual_kernel(Consts c, Bufs<T> b, PartLayout pl)
 {
+    __shared__ double lds[2 * RES_EDGES];
     if (b.sc->stop) return;
-    const int items = (c.m + 3) / 4;
+    const int items = c.nrp;
     const int blk = xcd_item(blockIdx.x, items);
     if (blk >= items) return;
-    const int e = blk * 4 + (int)(threadIdx.x >> 6);
-    if (e >= c.m) return;
-    residual_body<T>(c, b, pl, e);
+    residual_body<T>(c, b, pl, blk, lds);
 }
 
 // ----------------------------------------------------------------- control
-constexpr int CTRL_BLOCK = 256;
+constexpr int CTRL_BLOCK = 512;
 constexpr int NQ = 12;  // reduced quantities
 
 // One thread-strided pass over every partial segment with all loads independent, then
@@ -819,19 +995,22 @@ __device__ __forceinline__ void control_body(const Consts &c, const Bufs<T> &b, 
     const double *P = b.part;
     const long long seg[NQ] = {pl.dF, pl.dY, pl.e, pl.sup, pl.a, pl.b, pl.p, pl.conj, pl.rnum, pl.rden, pl.nonpos,
                                pl.yinf};
-    const long long len[NQ] = {c.nep, c.nnp, c.nep, c.nep, c.m, c.m, c.nnp, c.nnp, c.nnp, c.nnp, c.nnp, c.nnp};
+    const long long len[NQ] = {c.nep, c.nnp, c.nep, c.nep, c.nrp, c.nrp, c.nnp, c.nnp, c.nnp, c.nnp, c.nnp, c.nnp};
     const int nq = check ? NQ : 2;
     double acc[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
     long long most = 0;
     for (int q = 0; q < nq; ++q) most = len[q] > most ? len[q] : most;
+    // every load is unconditional (an index past its segment reads the segment's first entry,
+    // which is then discarded), so that the NQ loads of a pass are in flight together
+#pragma unroll 2
     for (long long x = threadIdx.x; x < most; x += CTRL_BLOCK) {
         double v[NQ];
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) v[q] = (q < nq && x < len[q]) ? P[seg[q] + x] : 0.0;
+        for (int q = 0; q < NQ; ++q) v[q] = P[seg[q] + (x < len[q] ? x : 0)];
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) acc[q] += v[q];
+        for (int q = 0; q < NQ; ++q) acc[q] += (q < nq && x < len[q]) ? v[q] : 0.0;
     }
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
@@ -940,19 +1119,21 @@ __device__ __forceinline__ bool slot_live(const SlotDesc<T> &d, long long G, lon
 // check variant is a kernel of its own and the register count of the regular kernel stays low.
 template <typename T, int EPT, int UTIL, bool CHECK>
 __device__ __forceinline__ void pool_body(const SlotDesc<T> &d, int parity, int j, bool partial, double *vsh,
-                                          double *red)
+                                          double *red, int2 *incs)
 {
-    if (CHECK) fused_body<T, EPT, UTIL, true, true, POOL_WAVES>(d.c, d.b, d.pl, parity, j, vsh, red);
-    else if (partial) fused_body<T, EPT, UTIL, false, true, POOL_WAVES>(d.c, d.b, d.pl, parity, j, vsh, red);
-    else fused_body<T, EPT, UTIL, false, false, POOL_WAVES>(d.c, d.b, d.pl, parity, j, vsh, red);
+    // the slot's stop flag was read by slot_live
+    if (CHECK) fused_body<T, EPT, UTIL, true, true, POOL_WAVES, false>(d.c, d.b, d.pl, parity, j, vsh, red, incs);
+    else if (partial)
+        fused_body<T, EPT, UTIL, false, true, POOL_WAVES, false>(d.c, d.b, d.pl, parity, j, vsh, red, incs);
+    else fused_body<T, EPT, UTIL, false, false, POOL_WAVES, false>(d.c, d.b, d.pl, parity, j, vsh, red, incs);
 }
 
 template <typename T, int EPT, bool CHECK>
 __device__ __forceinline__ void pool_util(const SlotDesc<T> &d, int parity, int j, bool partial, double *vsh,
-                                          double *red)
+                                          double *red, int2 *incs)
 {
-    if (d.c.utility == 0) pool_body<T, EPT, 0, CHECK>(d, parity, j, partial, vsh, red);
-    else pool_body<T, EPT, 1, CHECK>(d, parity, j, partial, vsh, red);
+    if (d.c.utility == 0) pool_body<T, EPT, 0, CHECK>(d, parity, j, partial, vsh, red, incs);
+    else pool_body<T, EPT, 1, CHECK>(d, parity, j, partial, vsh, red, incs);
 }
 
 template <typename T, bool CHECK>
@@ -961,6 +1142,7 @@ __global__ __launch_bounds__(64 * POOL_WAVES) void pool_fused_kernel(const SlotD
 {
     extern __shared__ double vsh[];
     __shared__ double red[2 * POOL_WAVES];
+    __shared__ int2 incs[FUSED_INC_CHUNK];
     const int2 wk = work[blockIdx.x];
     const SlotDesc<T> &d = slots[wk.x];
     long long k;
@@ -968,22 +1150,22 @@ __global__ __launch_bounds__(64 * POOL_WAVES) void pool_fused_kernel(const SlotD
     const int parity = d.par0 ^ (int)((G - d.G0) & 1);
     const bool partial = CHECK || adapts_at(d.c, k);
     const int n = d.c.n;
-    if (n <= 64) pool_util<T, 1, CHECK>(d, parity, wk.y, partial, vsh, red);
-    else if (n <= 128) pool_util<T, 2, CHECK>(d, parity, wk.y, partial, vsh, red);
-    else if (n <= 256) pool_util<T, 4, CHECK>(d, parity, wk.y, partial, vsh, red);
-    else pool_util<T, 8, CHECK>(d, parity, wk.y, partial, vsh, red);
+    if (n <= 64) pool_util<T, 1, CHECK>(d, parity, wk.y, partial, vsh, red, incs);
+    else if (n <= 128) pool_util<T, 2, CHECK>(d, parity, wk.y, partial, vsh, red, incs);
+    else if (n <= 256) pool_util<T, 4, CHECK>(d, parity, wk.y, partial, vsh, red, incs);
+    else pool_util<T, 8, CHECK>(d, parity, wk.y, partial, vsh, red, incs);
 }
 
-// grid (ceil(max m / 4), slots): one wave per edge of a slot
+// grid (max over slots of the residual blocks, slots)
 template <typename T>
-__global__ __launch_bounds__(256) void pool_residual_kernel(const SlotDesc<T> *slots, long long G)
+__global__ __launch_bounds__(64 * RES_EDGES) void pool_residual_kernel(const SlotDesc<T> *slots, long long G)
 {
+    __shared__ double lds[2 * RES_EDGES];
     const SlotDesc<T> &d = slots[blockIdx.y];
     long long k;
     if (!slot_live(d, G, k)) return;
-    const int e = (int)blockIdx.x * 4 + (int)(threadIdx.x >> 6);
-    if (e >= d.c.m) return;
-    residual_body<T>(d.c, d.b, d.pl, e);
+    if ((int)blockIdx.x >= d.c.nrp) return;
+    residual_body<T>(d.c, d.b, d.pl, (int)blockIdx.x, lds);
 }
 
 // one block per slot; acts on the slots whose iteration G adapted omega or was checked
@@ -1012,16 +1194,26 @@ __global__ void pool_gather_kernel(const SlotDesc<T> *slots, int nslots, DevScal
 // `bytes`-byte entries: enough lanes to cover n, with a 256-thread block (four waves) for
 // large n so that several blocks stay resident on a CU, and 512 threads for the largest
 // FP64 columns to keep the per-lane register count bounded.
+// Tail-grouped edge phase: each lane holds 2 * NV * VEC iterate values (F and q) and NV * VEC
+// FP64 out-edge sums; eight waves per tail node from n = 4096 on (FP32) keep that near
+// 100 VGPRs, sixteen for FP64 beyond n = 8192.
 EdgeShape edge_shape_for(int n, int bytes)
 {
     const int vec = 16 / bytes;
     if (n <= 64 * vec) return {1, 1};
     if (n <= 128 * vec) return {1, 2};
-    const int nvs[] = {1, 2, 4, 8, 12, 16};
-    for (int nv : nvs)
-        if (n <= 256 * vec * nv && (bytes == 4 || nv <= 8)) return {4, nv};
+    const int nv4[] = {1, 2, 4};
+    for (int nv : nv4)
+        if (n <= 256 * vec * nv) return {4, nv};
+    if (bytes == 4) {
+        const int nv8[] = {3, 4, 6, 8};
+        for (int nv : nv8)
+            if (n <= 512 * vec * nv) return {8, nv};
+        return {8, 8};
+    }
+    if (n <= 512 * vec * 4) return {8, 4};
     if (n <= 512 * vec * 8) return {8, 8};
-    return {8, 16};
+    return {16, 8};
 }
 
 int node_block_for(int n) { return n <= 512 ? 64 : 256; }
@@ -1037,7 +1229,7 @@ template <typename T, int WPE, int NV>
 static void edge_go(const Consts &c, const Bufs<T> &b, const PartLayout &pl, bool check, bool partial,
                     hipStream_t st)
 {
-    const dim3 grid(xcd_grid(WPE == 1 ? (c.m + 3) / 4 : c.m)), block(WPE == 1 ? 256 : 64 * WPE);
+    const dim3 grid(xcd_grid(WPE == 1 ? (c.n + 3) / 4 : c.n)), block(WPE == 1 ? 256 : 64 * WPE);
     if (check)
         hipLaunchKernelGGL((edge_kernel<T, WPE, NV, true, true>), grid, block, 0, st, c, b, pl);
     else if (partial)
@@ -1057,13 +1249,13 @@ hipError_t launch_edge(const Consts &c, const Bufs<T> &b, const PartLayout &pl, 
     MCF_EDGE_CASE(4, 1)
     MCF_EDGE_CASE(4, 2)
     MCF_EDGE_CASE(4, 4)
-    MCF_EDGE_CASE(4, 8)
+    MCF_EDGE_CASE(8, 4)
+    MCF_EDGE_CASE(8, 8)
     if constexpr (sizeof(T) == 4) {
-        MCF_EDGE_CASE(4, 12)
-        MCF_EDGE_CASE(4, 16)
+        MCF_EDGE_CASE(8, 3)
+        MCF_EDGE_CASE(8, 6)
     } else {
-        MCF_EDGE_CASE(8, 8)
-        MCF_EDGE_CASE(8, 16)
+        MCF_EDGE_CASE(16, 8)
     }
 #undef MCF_EDGE_CASE
     return hipErrorInvalidValue;
@@ -1130,7 +1322,7 @@ hipError_t launch_fused(const Consts &c, const Bufs<T> &b, const PartLayout &pl,
 template <typename T>
 hipError_t launch_residual(const Consts &c, const Bufs<T> &b, const PartLayout &pl, EdgeShape, hipStream_t st)
 {
-    hipLaunchKernelGGL(residual_kernel<T>, dim3(xcd_grid((c.m + 3) / 4)), dim3(256), 0, st, c, b, pl);
+    hipLaunchKernelGGL(residual_kernel<T>, dim3(xcd_grid(c.nrp)), dim3(64 * RES_EDGES), 0, st, c, b, pl);
     return hipGetLastError();
 }
 
@@ -1140,6 +1332,13 @@ hipError_t launch_control(const Consts &c, const Bufs<T> &b, const PartLayout &p
 {
     hipLaunchKernelGGL(control_kernel<T>, dim3(1), dim3(CTRL_BLOCK), 0, st, c, b, pl, check ? 1 : 0, adapt ? 1 : 0,
                        k_after);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_p_from_f(const Consts &c, const Bufs<T> &b, hipStream_t st)
+{
+    hipLaunchKernelGGL((p_from_f_kernel<T, 256>), dim3((c.n + 255) / 256, c.n), dim3(256), 0, st, c, b);
     return hipGetLastError();
 }
 
@@ -1160,7 +1359,8 @@ hipError_t launch_pool_iteration(const SlotDesc<T> *slots, const int2 *work, int
     else
         hipLaunchKernelGGL((pool_fused_kernel<T, false>), dim3(nwork), dim3(64 * POOL_WAVES), lds, st, slots, work, G);
     if (check)
-        hipLaunchKernelGGL(pool_residual_kernel<T>, dim3((max_m + 3) / 4, nslots), dim3(256), 0, st, slots, G);
+        hipLaunchKernelGGL(pool_residual_kernel<T>, dim3((max_m + RES_EDGES - 1) / RES_EDGES, nslots),
+                           dim3(64 * RES_EDGES), 0, st, slots, G);
     if (control)
         hipLaunchKernelGGL(pool_control_kernel<T>, dim3(nslots), dim3(CTRL_BLOCK), 0, st, slots, G, check ? 1 : 0);
     return hipGetLastError();
@@ -1186,6 +1386,7 @@ hipError_t launch_pool_gather(const SlotDesc<T> *slots, int nslots, DevScalars *
     template hipError_t launch_control<T>(const Consts &, const Bufs<T> &, const PartLayout &, bool, bool,       \
                                           long long, hipStream_t);                                              \
     template hipError_t launch_poison<T>(const Bufs<T> &, int, long long, hipStream_t);                      \
+    template hipError_t launch_p_from_f<T>(const Consts &, const Bufs<T> &, hipStream_t);                    \
     template hipError_t launch_pool_iteration<T>(const SlotDesc<T> *, const int2 *, int, int, int, int, long long, \
                                                  bool, bool, hipStream_t);                                    \
     template hipError_t launch_pool_gather<T>(const SlotDesc<T> *, int, DevScalars *, hipStream_t);

@@ -53,7 +53,7 @@ PartLayout part_layout(int m, int nb)
 
 // Byte offsets of every device buffer inside one allocation.
 struct Plan {
-    size_t F, Fbar, Fhat, D, Y, W, That, Up, cap, mu, F2, Y2, mu2, tail, head, out_off, in_off, in_edge, inc_off,
+    size_t F, Fhat, D, Y, W, P, Sout, That, Up, cap, mu, F2, Y2, mu2, tail, head, out_off, in_off, in_edge, inc_off,
         inc, part, sc, total;
 };
 
@@ -69,11 +69,12 @@ Plan make_plan(int n, int m, int precision, bool fused)
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes); return at; };
     p.F = take(nm * es);
-    p.Fbar = take(fused ? 0 : nm * es);  // the fused iteration never stores Fbar
     p.Fhat = take(nm * es);
     p.D = take(nm * es);
     p.Y = take(nn * es);
     p.W = take(nn * es);
+    p.P = take(fused ? 0 : nn * es);  // two-phase iteration: P = F A^T and the out-edge sums
+    p.Sout = take(fused ? 0 : nn * es);
     p.That = take(nn * 8);
     p.Up = take(nn * 8);
     p.cap = take((size_t)m * 8);
@@ -123,7 +124,7 @@ struct mcf_solver {
     size_t cur_F() const { return parity(k) ? plan.F2 : plan.F; }
     size_t cur_Y() const { return parity(k) ? plan.Y2 : plan.Y; }
     double seconds = 0.0;
-    // kernel timing of the edge phase
+    // kernel timing of the iteration's main launches (fused, or edge + node)
     bool timing = false;
     std::vector<hipEvent_t> ev;  // pairs (start, stop) recorded during the current drive
     size_t ev_used = 0, ev_done = 0;
@@ -135,7 +136,8 @@ struct mcf_solver {
     {
         Bufs<T> b;
         b.F = (T *)(base + plan.F);
-        b.Fbar = (T *)(base + plan.Fbar);
+        b.P = (T *)(base + plan.P);
+        b.Sout = (T *)(base + plan.Sout);
         b.Fhat = (T *)(base + plan.Fhat);
         b.D = (T *)(base + plan.D);
         b.Y = (T *)(base + plan.Y);
@@ -349,8 +351,8 @@ int enqueue_block(mcf_solver *s, long long k0, long long count)
             if (timed) MCF_TRY(hipEventRecord(e1, s->stream));
         } else {
             MCF_TRY(launch_edge<T>(s->c, b, s->pl, s->sh, check, partial, s->stream));
-            if (timed) MCF_TRY(hipEventRecord(e1, s->stream));
             MCF_TRY(launch_node<T>(s->c, b, s->pl, check, partial, s->stream));
+            if (timed) MCF_TRY(hipEventRecord(e1, s->stream));
         }
         if (check) MCF_TRY(launch_residual<T>(s->c, b, s->pl, s->sh, s->stream));
         if (partial) MCF_TRY(launch_control<T>(s->c, b, s->pl, check, adapt, k + 1, s->stream));
@@ -574,7 +576,8 @@ int mcf_create(int32_t n, int32_t m, const int32_t *tail, const int32_t *head, c
     c.nblk_node = node_blocks(n);
     c.node_block = node_block_for(n);
     c.fused = fused ? 1 : 0;
-    c.nep = fused ? n : m;
+    c.nep = n;  // edge quantities are added per tail node
+    c.nrp = (m + RES_EDGES - 1) / RES_EDGES;
     c.nnp = fused ? n : c.nblk_node;
 
     int rc = MCF_OK;
@@ -714,6 +717,11 @@ int mcf_set_state(mcf_solver *s, const double *F, const double *Y, const mcf_sca
     int rc = upload_any(s, s->plan.F, s->m, true, F);
     if (!rc && Y) rc = upload_any(s, s->plan.Y, s->n, false, Y);
     if (rc) return rc;
+    if (!s->c.fused) {
+        // the two-phase iteration carries P = F A^T of the current F
+        MCF_TRY(s->precision == MCF_FP32 ? launch_p_from_f<float>(s->c, s->bufs<float>(), s->stream)
+                                         : launch_p_from_f<double>(s->c, s->bufs<double>(), s->stream));
+    }
     if ((rc = pull_scalars(s))) return rc;
     if (sc) s->k = sc->k;
     s->anchor_k = s->k;
