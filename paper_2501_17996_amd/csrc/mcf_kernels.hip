@@ -29,10 +29,12 @@ namespace mcf {
 // leave every lane of a 16-lane row with the row total; the four row totals, read
 // from lanes 0/16/32/48, are added in row order.  The result is uniform (scalar) and
 // its rounding order is fixed.
+// The lane moves used here (quad permutes, row rotates) read a valid lane for every lane, so
+// the destination's previous value is never kept and needs no initialisation.
 template <int CTRL>
 __device__ __forceinline__ int dpp_i32(int v)
 {
-    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+    return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, true);
 }
 
 template <int CTRL>
@@ -64,6 +66,28 @@ __device__ __forceinline__ double wave_sum(double v)
     v += dpp_f64<DPP_ROW_ROR4>(v);
     v += dpp_f64<DPP_ROW_ROR8>(v);
     return ((lane_f64(v, 0) + lane_f64(v, 16)) + lane_f64(v, 32)) + lane_f64(v, 48);
+}
+
+// Two wave sums with their DPP steps interleaved, so that the two dependency chains overlap;
+// each result is bitwise the one wave_sum gives.
+__device__ __forceinline__ void wave_sum2(double &x, double &y)
+{
+    x += dpp_f64<DPP_QUAD_XOR1>(x);
+    y += dpp_f64<DPP_QUAD_XOR1>(y);
+    x += dpp_f64<DPP_QUAD_XOR2>(x);
+    y += dpp_f64<DPP_QUAD_XOR2>(y);
+    x += dpp_f64<DPP_ROW_ROR4>(x);
+    y += dpp_f64<DPP_ROW_ROR4>(y);
+    x += dpp_f64<DPP_ROW_ROR8>(x);
+    y += dpp_f64<DPP_ROW_ROR8>(y);
+    x = ((lane_f64(x, 0) + lane_f64(x, 16)) + lane_f64(x, 32)) + lane_f64(x, 48);
+    y = ((lane_f64(y, 0) + lane_f64(y, 16)) + lane_f64(y, 32)) + lane_f64(y, 48);
+}
+
+// Number of lanes of the wave for which p holds (wave-uniform): a ballot, no reduction chain.
+__device__ __forceinline__ int wave_count(bool p)
+{
+    return __popcll(__ballot(p));
 }
 
 __device__ __forceinline__ int wave_sum(int v)
@@ -133,6 +157,29 @@ __device__ __forceinline__ void group_sum(double &x, int &y, double *lds)
         }
         x = sx;
         y = (int)sy;
+    }
+}
+
+// Adds K wave-uniform values over the NW waves of a group, in wave order, through LDS
+// (`lds` holds K * NW doubles and is private to the group).  NW == 1 needs nothing.
+template <int NW, int K>
+__device__ __forceinline__ void group_combine(double (&x)[K], double *lds)
+{
+    if constexpr (NW > 1) {
+        const int lane = threadIdx.x & 63, wid = (threadIdx.x >> 6) % NW;
+        __syncthreads();
+        if (lane == 0) {
+#pragma unroll
+            for (int k = 0; k < K; ++k) lds[k * NW + wid] = x[k];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            double s = 0.0;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) s += lds[k * NW + w];
+            x[k] = s;
+        }
     }
 }
 
@@ -341,7 +388,7 @@ __global__ __launch_bounds__(WPE == 1 ? 256 : 64 * WPE) void edge_kernel(Consts 
     constexpr int VEC = Vec<T>::N;
     constexpr int LANES = 64 * WPE;  // threads per tail node
     constexpr int NT = WPE == 1 ? 256 : 64 * WPE;
-    __shared__ double lds[2 * WPE];
+    __shared__ double lds[4 * WPE];
     // the out-edge sums live in LDS, one 16-byte vector per (vector slot, thread): in
     // registers they would cost the occupancy that keeps enough loads in flight
     __shared__ typename Vec<T>::type sol[NV * NT];
@@ -394,16 +441,17 @@ __global__ __launch_bounds__(WPE == 1 ? 256 : 64 * WPE) void edge_kernel(Consts 
         // Sums over a support {q > thr}: each 16-byte vector is first added in the iterate
         // type (in a fixed order), then in FP64.  Converting per vector rather than per entry
         // keeps the compiler from holding an FP64 copy of every q across the passes.
+        // The support sizes are counted wave by wave with ballots (no reduction chain).
         auto support_sum = [&](T thr, double &s, int &cnt) {
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
                 T part = T(0);
 #pragma unroll
-                for (int u = 0; u < VEC; ++u)
-                    if (q[v][u] > thr) {
-                        part += q[v][u];
-                        ++cnt;
-                    }
+                for (int u = 0; u < VEC; ++u) {
+                    const bool in = q[v][u] > thr;
+                    if (in) part += q[v][u];
+                    cnt += wave_count(in);
+                }
                 s += (double)part;
             }
         };
@@ -412,8 +460,15 @@ __global__ __launch_bounds__(WPE == 1 ? 256 : 64 * WPE) void edge_kernel(Consts 
         int cp = 0, cw = 0;
         support_sum(T(0), sp, cp);
         support_sum(thr0, sw, cw);
-        group_sum<WPE>(sp, cp, lds);
-        group_sum<WPE>(sw, cw, lds);
+        wave_sum2(sp, sw);
+        {
+            double g[4] = {sp, sw, (double)cp, (double)cw};
+            group_combine<WPE, 4>(g, lds);
+            sp = g[0];
+            sw = g[1];
+            cp = (int)g[2];
+            cw = (int)g[3];
+        }
         double mu = 0.0;
         if (sp > cap) {
             mu = (sp - cap) / cp;
@@ -425,12 +480,29 @@ __global__ __launch_bounds__(WPE == 1 ? 256 : 64 * WPE) void edge_kernel(Consts 
                     prev = mw >= mu0 ? cw : 0x7fffffff;  // {q > mu0} contains {q > mw} only if mw >= mu0
                 }
             }
+            // each pass counts the support first; only a support that shrank needs its sum
             for (int pass = 0; pass <= n; ++pass) {
-                double s = 0.0;
+                const T thr = below(mu, T(0));
                 int cnt = 0;
-                support_sum(below(mu, T(0)), s, cnt);
-                group_sum<WPE>(s, cnt, lds);
+#pragma unroll
+                for (int v = 0; v < NV; ++v)
+#pragma unroll
+                    for (int u = 0; u < VEC; ++u) cnt += wave_count(q[v][u] > thr);
+                {
+                    double g[1] = {(double)cnt};
+                    group_combine<WPE, 1>(g, lds);
+                    cnt = (int)g[0];
+                }
                 if (cnt >= prev) break;
+                double s = 0.0;
+                int dummy = 0;
+                support_sum(thr, s, dummy);
+                s = wave_sum(s);
+                {
+                    double g[1] = {s};
+                    group_combine<WPE, 1>(g, lds);
+                    s = g[0];
+                }
                 mu = (s - cap) / cnt;
                 prev = cnt;
             }
@@ -743,17 +815,22 @@ __device__ __forceinline__ void fused_body(const Consts &c, const Bufs<T> &b, co
                 q[jj] = T(-1);
             }
         }
-        // the projection of Section 2.3 with the warm-started active-set search of edge_kernel
-        double sp = 0.0, sw = 0.0;
+        // the projection of Section 2.3 with the warm-started active-set search of edge_kernel:
+        // comparisons in the iterate type against thresholds rounded down (exact), each lane's
+        // entries added in the iterate type, lanes in FP64; support sizes by ballot
+        const T thr0 = below(mu0, T(0));
+        T psum = T(0), wsum = T(0);
         int cp = 0, cw = 0;
 #pragma unroll
         for (int jj = 0; jj < EPT; ++jj) {
-            const double qd = (double)q[jj];
-            if (qd > 0.0) { sp += qd; ++cp; }
-            if (qd > mu0) { sw += qd; ++cw; }
+            const bool ip = q[jj] > T(0), iw = q[jj] > thr0;
+            if (ip) psum += q[jj];
+            if (iw) wsum += q[jj];
+            cp += wave_count(ip);
+            cw += wave_count(iw);
         }
-        sp = wave_sum(sp); cp = wave_sum(cp);
-        sw = wave_sum(sw); cw = wave_sum(cw);
+        double sp = (double)psum, sw = (double)wsum;
+        wave_sum2(sp, sw);
         double mu = 0.0;
         if (sp > cap) {
             mu = (sp - cap) / cp;
@@ -765,15 +842,18 @@ __device__ __forceinline__ void fused_body(const Consts &c, const Bufs<T> &b, co
                     prev = mw >= mu0 ? cw : 0x7fffffff;
                 }
             }
+            // each pass counts the support first; only a support that shrank needs its sum
             for (int pass = 0; pass <= n; ++pass) {
-                double s = 0.0;
+                const T thr = below(mu, T(0));
                 int cnt = 0;
 #pragma unroll
-                for (int jj = 0; jj < EPT; ++jj)
-                    if ((double)q[jj] > mu) { s += (double)q[jj]; ++cnt; }
-                s = wave_sum(s);
-                cnt = wave_sum(cnt);
+                for (int jj = 0; jj < EPT; ++jj) cnt += wave_count(q[jj] > thr);
                 if (cnt >= prev) break;
+                T ps = T(0);
+#pragma unroll
+                for (int jj = 0; jj < EPT; ++jj)
+                    if (q[jj] > thr) ps += q[jj];
+                const double s = wave_sum((double)ps);
                 mu = (s - cap) / cnt;
                 prev = cnt;
             }
