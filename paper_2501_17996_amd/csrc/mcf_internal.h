@@ -74,6 +74,7 @@ struct Bufs {
     const int *inc_off;
     const int2 *inc;
     const double *cap;
+    const double *rcp;     // rcp[k] = 1/k for k = 1..n (support sizes of a projection)
     double *mu;            // per-edge multiplier of the last projection (warm start of the next one)
     double *part;
     DevScalars *sc;

@@ -471,10 +471,10 @@ __global__ __launch_bounds__(WPE == 1 ? 256 : 64 * WPE) void edge_kernel(Consts 
         }
         double mu = 0.0;
         if (sp > cap) {
-            mu = (sp - cap) / cp;
+            mu = (sp - cap) * b.rcp[cp];
             int prev = cp;  // mu came from S' = {q > 0}, a superset of {q > mu}
             if (cw > 0) {
-                const double mw = (sw - cap) / cw;
+                const double mw = (sw - cap) * b.rcp[cw];
                 if (mw > mu) {
                     mu = mw;
                     prev = mw >= mu0 ? cw : 0x7fffffff;  // {q > mu0} contains {q > mw} only if mw >= mu0
@@ -503,7 +503,7 @@ __global__ __launch_bounds__(WPE == 1 ? 256 : 64 * WPE) void edge_kernel(Consts 
                     group_combine<WPE, 1>(g, lds);
                     s = g[0];
                 }
-                mu = (s - cap) / cnt;
+                mu = (s - cap) * b.rcp[cnt];
                 prev = cnt;
             }
         }
@@ -833,10 +833,10 @@ __device__ __forceinline__ void fused_body(const Consts &c, const Bufs<T> &b, co
         wave_sum2(sp, sw);
         double mu = 0.0;
         if (sp > cap) {
-            mu = (sp - cap) / cp;
+            mu = (sp - cap) * b.rcp[cp];
             int prev = cp;
             if (cw > 0) {
-                const double mw = (sw - cap) / cw;
+                const double mw = (sw - cap) * b.rcp[cw];
                 if (mw > mu) {
                     mu = mw;
                     prev = mw >= mu0 ? cw : 0x7fffffff;
@@ -854,30 +854,31 @@ __device__ __forceinline__ void fused_body(const Consts &c, const Bufs<T> &b, co
                 for (int jj = 0; jj < EPT; ++jj)
                     if (q[jj] > thr) ps += q[jj];
                 const double s = wave_sum((double)ps);
-                mu = (s - cap) / cnt;
+                mu = (s - cap) * b.rcp[cnt];
                 prev = cnt;
             }
         }
+        // Fhat, Fbar and the relaxed F in the iterate type (V and the partials add in FP64)
         double gmax = -INFINITY;
+        const T mut = (T)mu, rhot = (T)rho, omrt = (T)omr;
 #pragma unroll
         for (int jj = 0; jj < EPT; ++jj) {
             const int i = lane + jj * 64;
             if (i < n) {
-                const double fod = (double)fo[jj];
-                const double fh = fmax((double)q[jj] - mu, 0.0);
-                const double fb = 2.0 * fh - fod;
-                vacc[jj] += out ? -fb : fb;
-                if (CHECK) tacc[jj] += out ? fh : -fh;  // T = -Fhat A^T
+                const T fh = q[jj] > mut ? q[jj] - mut : T(0);
+                const T fb = T(2) * fh - fo[jj];
+                vacc[jj] += (double)(out ? -fb : fb);
+                if (CHECK) tacc[jj] += (double)(out ? fh : -fh);  // T = -Fhat A^T
                 if (out) {
-                    const T fn = (T)(rho * fh + omr * fod);
+                    const T fn = rhot * fh + omrt * fo[jj];
                     Fn[(long long)e * ld + i] = fn;
                     if (PARTIAL) {
-                        const double d = (double)fn - fod;
+                        const double d = (double)fn - (double)fo[jj];
                         dsum += d * d;
                     }
                     if (CHECK) {
-                        b.Fhat[(long long)e * ld + i] = (T)fh;
-                        const T dd = (T)(fh - (double)q[jj]);
+                        b.Fhat[(long long)e * ld + i] = fh;
+                        const T dd = fh - q[jj];
                         b.D[(long long)e * ld + i] = dd;
                         esum += (double)dd * (double)dd;
                         gmax = fmax(gmax, (double)(ya[jj] - yjl[jj]));  // (Y A)_il of the leaving edge

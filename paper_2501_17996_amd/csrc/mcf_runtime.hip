@@ -53,7 +53,7 @@ PartLayout part_layout(int m, int nb)
 
 // Byte offsets of every device buffer inside one allocation.
 struct Plan {
-    size_t F, Fhat, D, Y, W, P, Sout, That, Up, cap, mu, F2, Y2, mu2, tail, head, out_off, in_off, in_edge, inc_off,
+    size_t F, Fhat, D, Y, W, P, Sout, That, Up, cap, rcp, mu, F2, Y2, mu2, tail, head, out_off, in_off, in_edge, inc_off,
         inc, part, sc, total;
 };
 
@@ -78,6 +78,7 @@ Plan make_plan(int n, int m, int precision, bool fused)
     p.That = take(nn * 8);
     p.Up = take(nn * 8);
     p.cap = take((size_t)m * 8);
+    p.rcp = take((size_t)(n + 1) * 8);
     p.mu = take((size_t)m * 8);
     p.F2 = take(fused ? nm * es : 0);  // ping-pong buffers of the fused iteration
     p.Y2 = take(fused ? nn * es : 0);
@@ -152,6 +153,7 @@ struct mcf_solver {
         b.inc_off = (const int *)(base + plan.inc_off);
         b.inc = (const int2 *)(base + plan.inc);
         b.cap = (const double *)(base + plan.cap);
+        b.rcp = (const double *)(base + plan.rcp);
         b.mu = (double *)(base + plan.mu);
         b.F2 = (T *)(base + plan.F2);
         b.Y2 = (T *)(base + plan.Y2);
@@ -246,6 +248,11 @@ int upload_problem(mcf_solver *s, const int *tail, const int *head, const double
     hipStream_t st = s->stream;
     MCF_TRY(hipMemcpyAsync(b + p.W, W.data(), W.size() * sizeof(T), hipMemcpyHostToDevice, st));
     MCF_TRY(hipMemcpyAsync(b + p.cap, c.data(), m * 8, hipMemcpyHostToDevice, st));
+    // 1/k for the multiplier mu = (sum_S q - c)/|S| of the projection (a product, within one
+    // rounding of the quotient)
+    std::vector<double> rcp(n + 1, 0.0);
+    for (int k = 1; k <= n; ++k) rcp[k] = 1.0 / (double)k;
+    MCF_TRY(hipMemcpyAsync(b + p.rcp, rcp.data(), (n + 1) * 8, hipMemcpyHostToDevice, st));
     MCF_TRY(hipMemcpyAsync(b + p.tail, t.data(), m * 4, hipMemcpyHostToDevice, st));
     MCF_TRY(hipMemcpyAsync(b + p.head, h.data(), m * 4, hipMemcpyHostToDevice, st));
     MCF_TRY(hipMemcpyAsync(b + p.out_off, out_off.data(), (n + 1) * 4, hipMemcpyHostToDevice, st));
