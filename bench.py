@@ -245,7 +245,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
-    ap.add_argument("--check-every", type=int, default=20)
+    ap.add_argument("--check-every", type=int, default=None,
+                    help="residual check interval: default 50 for single solves (a check costs about two "
+                         "iterations; a solve overshoots by fewer than K), 20 for the serving loop")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-mode", type=int, default=0, help="0 auto, 1 two-phase, 2 fused")
@@ -276,6 +278,8 @@ def main():
     if args.workload == "knn":
         knn_bench(args)
         return
+    if args.check_every is None:
+        args.check_every = 20 if args.workload == "serve" else 50
     if args.workload == "serve":
         if args.adapt_until is None:
             args.adapt_until = 1000

@@ -92,15 +92,17 @@ EdgeShape edge_shape_for(int n, int bytes);
 template <typename T>
 hipError_t launch_init(const Consts &c, const Bufs<T> &b, double omega0, hipStream_t st);
 // `partial`: also write the ||dF||^2 / ||dY||^2 partials (iterations that end in a control launch).
+// `e0`, `e1` (may be null): events recorded by the dispatch itself at the start and the end of
+// the kernel (for the roofline timing).
 template <typename T>
 hipError_t launch_edge(const Consts &c, const Bufs<T> &b, const PartLayout &pl, EdgeShape sh, bool check,
-                       bool partial, hipStream_t st);
+                       bool partial, hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 template <typename T>
 hipError_t launch_node(const Consts &c, const Bufs<T> &b, const PartLayout &pl, bool check, bool partial,
-                       hipStream_t st);
+                       hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 template <typename T>
 hipError_t launch_fused(const Consts &c, const Bufs<T> &b, const PartLayout &pl, EdgeShape sh, int parity,
-                        bool check, bool partial, hipStream_t st);
+                        bool check, bool partial, hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 template <typename T>
 hipError_t launch_residual(const Consts &c, const Bufs<T> &b, const PartLayout &pl, EdgeShape sh,
                            hipStream_t st);

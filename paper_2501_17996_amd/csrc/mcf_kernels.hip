@@ -18,6 +18,7 @@
 // iterations the edge and node phases also produce Fhat, D = Fhat - Q, T = -Fhat A^T
 // and U' = u'(T), and a residual pass forms ||G||^2 and <G, D> for r(Q) of (e-res).
 // No atomics anywhere: every sum has a fixed order, so results are deterministic.
+#include <hip/hip_ext.h>
 #include <math.h>
 
 #include "mcf_internal.h"
@@ -1308,23 +1309,23 @@ hipError_t launch_init(const Consts &c, const Bufs<T> &b, double omega0, hipStre
 
 template <typename T, int WPE, int NV>
 static void edge_go(const Consts &c, const Bufs<T> &b, const PartLayout &pl, bool check, bool partial,
-                    hipStream_t st)
+                    hipStream_t st, hipEvent_t e0, hipEvent_t e1)
 {
     const dim3 grid(xcd_grid(WPE == 1 ? (c.n + 3) / 4 : c.n)), block(WPE == 1 ? 256 : 64 * WPE);
     if (check)
-        hipLaunchKernelGGL((edge_kernel<T, WPE, NV, true, true>), grid, block, 0, st, c, b, pl);
+        hipExtLaunchKernelGGL((edge_kernel<T, WPE, NV, true, true>), grid, block, 0, st, e0, e1, 0, c, b, pl);
     else if (partial)
-        hipLaunchKernelGGL((edge_kernel<T, WPE, NV, false, true>), grid, block, 0, st, c, b, pl);
+        hipExtLaunchKernelGGL((edge_kernel<T, WPE, NV, false, true>), grid, block, 0, st, e0, e1, 0, c, b, pl);
     else
-        hipLaunchKernelGGL((edge_kernel<T, WPE, NV, false, false>), grid, block, 0, st, c, b, pl);
+        hipExtLaunchKernelGGL((edge_kernel<T, WPE, NV, false, false>), grid, block, 0, st, e0, e1, 0, c, b, pl);
 }
 
 template <typename T>
 hipError_t launch_edge(const Consts &c, const Bufs<T> &b, const PartLayout &pl, EdgeShape sh, bool check,
-                       bool partial, hipStream_t st)
+                       bool partial, hipStream_t st, hipEvent_t e0, hipEvent_t e1)
 {
 #define MCF_EDGE_CASE(W, V) \
-    if (sh.wpe == W && sh.ept == V) { edge_go<T, W, V>(c, b, pl, check, partial, st); return hipGetLastError(); }
+    if (sh.wpe == W && sh.ept == V) { edge_go<T, W, V>(c, b, pl, check, partial, st, e0, e1); return hipGetLastError(); }
     MCF_EDGE_CASE(1, 1)
     MCF_EDGE_CASE(1, 2)
     MCF_EDGE_CASE(4, 1)
@@ -1343,53 +1344,55 @@ hipError_t launch_edge(const Consts &c, const Bufs<T> &b, const PartLayout &pl, 
 }
 
 template <typename T, int NB, int UTIL>
-static void node_go(const Consts &c, const Bufs<T> &b, const PartLayout &pl, bool check, bool partial, hipStream_t st)
+static void node_go(const Consts &c, const Bufs<T> &b, const PartLayout &pl, bool check, bool partial, hipStream_t st,
+                    hipEvent_t e0, hipEvent_t e1)
 {
     const dim3 grid((c.n + NB - 1) / NB, c.n);
-    if (check) hipLaunchKernelGGL((node_kernel<T, NB, UTIL, true, true>), grid, dim3(NB), 0, st, c, b, pl);
-    else if (partial) hipLaunchKernelGGL((node_kernel<T, NB, UTIL, false, true>), grid, dim3(NB), 0, st, c, b, pl);
-    else hipLaunchKernelGGL((node_kernel<T, NB, UTIL, false, false>), grid, dim3(NB), 0, st, c, b, pl);
+    if (check) hipExtLaunchKernelGGL((node_kernel<T, NB, UTIL, true, true>), grid, dim3(NB), 0, st, e0, e1, 0, c, b, pl);
+    else if (partial) hipExtLaunchKernelGGL((node_kernel<T, NB, UTIL, false, true>), grid, dim3(NB), 0, st, e0, e1, 0, c, b, pl);
+    else hipExtLaunchKernelGGL((node_kernel<T, NB, UTIL, false, false>), grid, dim3(NB), 0, st, e0, e1, 0, c, b, pl);
 }
 
 template <typename T>
 hipError_t launch_node(const Consts &c, const Bufs<T> &b, const PartLayout &pl, bool check, bool partial,
-                       hipStream_t st)
+                       hipStream_t st, hipEvent_t e0, hipEvent_t e1)
 {
     if (c.node_block == 64) {
-        if (c.utility == 0) node_go<T, 64, 0>(c, b, pl, check, partial, st);
-        else node_go<T, 64, 1>(c, b, pl, check, partial, st);
+        if (c.utility == 0) node_go<T, 64, 0>(c, b, pl, check, partial, st, e0, e1);
+        else node_go<T, 64, 1>(c, b, pl, check, partial, st, e0, e1);
     } else {
-        if (c.utility == 0) node_go<T, 256, 0>(c, b, pl, check, partial, st);
-        else node_go<T, 256, 1>(c, b, pl, check, partial, st);
+        if (c.utility == 0) node_go<T, 256, 0>(c, b, pl, check, partial, st, e0, e1);
+        else node_go<T, 256, 1>(c, b, pl, check, partial, st, e0, e1);
     }
     return hipGetLastError();
 }
 
 template <typename T, int EPT, int UTIL>
 static void fused_go(const Consts &c, const Bufs<T> &b, const PartLayout &pl, int parity, bool check, bool partial,
-                     hipStream_t st)
+                     hipStream_t st, hipEvent_t e0, hipEvent_t e1)
 {
     constexpr int NWC = fused_waves<EPT, true>(), NWR = fused_waves<EPT, false>();
+    constexpr size_t VW = EPT * 64 * sizeof(double);  // LDS bytes per wave for V (and T)
     const dim3 grid(c.n);
     if (check)
-        hipLaunchKernelGGL((fused_kernel<T, EPT, UTIL, true, true>), grid, dim3(64 * NWC),
-                           2 * NWC * EPT * 64 * sizeof(double), st, c, b, pl, parity);
+        hipExtLaunchKernelGGL((fused_kernel<T, EPT, UTIL, true, true>), grid, dim3(64 * NWC), 2 * NWC * VW, st, e0, e1,
+                              0, c, b, pl, parity);
     else if (partial)
-        hipLaunchKernelGGL((fused_kernel<T, EPT, UTIL, false, true>), grid, dim3(64 * NWR),
-                           NWR * EPT * 64 * sizeof(double), st, c, b, pl, parity);
+        hipExtLaunchKernelGGL((fused_kernel<T, EPT, UTIL, false, true>), grid, dim3(64 * NWR), NWR * VW, st, e0, e1,
+                              0, c, b, pl, parity);
     else
-        hipLaunchKernelGGL((fused_kernel<T, EPT, UTIL, false, false>), grid, dim3(64 * NWR),
-                           NWR * EPT * 64 * sizeof(double), st, c, b, pl, parity);
+        hipExtLaunchKernelGGL((fused_kernel<T, EPT, UTIL, false, false>), grid, dim3(64 * NWR), NWR * VW, st, e0, e1,
+                              0, c, b, pl, parity);
 }
 
 template <typename T>
 hipError_t launch_fused(const Consts &c, const Bufs<T> &b, const PartLayout &pl, EdgeShape, int parity, bool check,
-                        bool partial, hipStream_t st)
+                        bool partial, hipStream_t st, hipEvent_t e0, hipEvent_t e1)
 {
 #define MCF_FUSED_CASE(E)                                                  \
     if (c.n <= 64 * E) {                                                   \
-        if (c.utility == 0) fused_go<T, E, 0>(c, b, pl, parity, check, partial, st); \
-        else fused_go<T, E, 1>(c, b, pl, parity, check, partial, st);      \
+        if (c.utility == 0) fused_go<T, E, 0>(c, b, pl, parity, check, partial, st, e0, e1); \
+        else fused_go<T, E, 1>(c, b, pl, parity, check, partial, st, e0, e1); \
         return hipGetLastError();                                          \
     }
     MCF_FUSED_CASE(1)
@@ -1457,11 +1460,11 @@ hipError_t launch_pool_gather(const SlotDesc<T> *slots, int nslots, DevScalars *
 #define MCF_INSTANTIATE(T)                                                                                      \
     template hipError_t launch_init<T>(const Consts &, const Bufs<T> &, double, hipStream_t);                   \
     template hipError_t launch_edge<T>(const Consts &, const Bufs<T> &, const PartLayout &, EdgeShape, bool,     \
-                                       bool, hipStream_t);                                                      \
+                                       bool, hipStream_t, hipEvent_t, hipEvent_t);                              \
     template hipError_t launch_node<T>(const Consts &, const Bufs<T> &, const PartLayout &, bool, bool,          \
-                                       hipStream_t);                                                            \
+                                       hipStream_t, hipEvent_t, hipEvent_t);                                    \
     template hipError_t launch_fused<T>(const Consts &, const Bufs<T> &, const PartLayout &, EdgeShape, int, bool, \
-                                        bool, hipStream_t);                                                     \
+                                        bool, hipStream_t, hipEvent_t, hipEvent_t);                             \
     template hipError_t launch_residual<T>(const Consts &, const Bufs<T> &, const PartLayout &, EdgeShape,       \
                                            hipStream_t);                                                        \
     template hipError_t launch_control<T>(const Consts &, const Bufs<T> &, const PartLayout &, bool, bool,       \
