@@ -186,7 +186,7 @@ def test_c2_fp32_trajectory_tracks_oracle(M):
 
 
 # ------------------------------------------------ power utility, larger shapes
-@pytest.mark.parametrize("gamma", [0.5, 0.3])
+@pytest.mark.parametrize("gamma", [0.5, 0.3, 0.1, 0.9])
 def test_power_utility_trajectory(M, gamma):
     inst = I.ring_instance(150, 6, seed=3, utility=I.UTIL_POWER, gamma=gamma)
     S = gpu_solver(M, inst)
@@ -199,6 +199,43 @@ def test_power_utility_trajectory(M, gamma):
     S.run(300)
     O.run(300, check=False)
     assert_state_close(S, O, rtol=1e-9, what=f"power {gamma} k 340")
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_knn_paper_workload_trajectory(M, mode):
+    """The paper's own instance family (Section 3.1: q-nearest-neighbour bidirected graph,
+    log-uniform capacities and weights), FP64, both kernel organisations."""
+    inst = I.knn_geometric(80, 8, 3)
+    S = gpu_solver(M, inst, kernel_mode=mode)
+    O = oracle.OracleSolver(inst, threads=THREADS)
+    done = 0
+    for k in (1, 2, 50, 101, 300):
+        S.run(k - done)
+        O.run(k - done - 1, check=False)
+        mo = O.step(check=True)
+        done = k
+        assert_state_close(S, O, what=f"knn k={k}")
+        assert_metrics_close(S.status(), mo, what=f"knn k {k}")
+
+
+def test_knn_frozen_primal_weight_converges(M):
+    """On the paper's kNN workload the primal weight adapted for the whole run drifts and the
+    iterate loses feasibility again; frozen at iteration 2000 (Section 2.4) the solve converges.
+    The GPU's stopping iteration and objective are checked against the oracle run with the
+    same freeze."""
+    inst = I.knn_geometric(100, 10, 0)
+    S = gpu_solver(M, inst, tol=1e-4, check_every=100, max_iter=40000, adapt_until=2000)
+    st = S.solve()
+    assert st["state_name"] == "converged", st
+    k = st["iters"]
+    O = oracle.OracleSolver(inst, threads=THREADS, adapt_until=2000)
+    O.run(k - 1, check=False)
+    mo = O.step(check=True)
+    assert mo["rel_kkt"] <= 1e-4
+    assert st["primal_obj"] == pytest.approx(mo["primal_obj"], rel=1e-9)
+    assert st["dual_obj"] == pytest.approx(mo["dual_obj"], rel=1e-9)
+    assert st["rel_gap"] < 1e-6
+    print(f"knn n=100 frozen omega: converged at {k}, rel_gap {st['rel_gap']:.2e}")
 
 
 def test_c3_fp64_first_iterations(M):

@@ -136,7 +136,7 @@ def test_prox_power_half_cubic(orc, y, beta, w):
     assert z == pytest.approx(_prox_conj_by_moreau(y, beta, w, 1, 0.5), rel=1e-6, abs=1e-8 * max(1.0, abs(y)))
 
 
-@pytest.mark.parametrize("gamma", [0.2, 0.35, 0.7, 0.9])
+@pytest.mark.parametrize("gamma", [0.1, 0.2, 0.35, 0.7, 0.9])
 @pytest.mark.parametrize("y", [-3.0, -0.1, 0.0, 1.5])
 def test_prox_power_general_gamma(orc, gamma, y):
     beta, w = 0.4, 1.2
