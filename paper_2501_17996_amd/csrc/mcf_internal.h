@@ -33,6 +33,7 @@ struct Consts {
     int node_block;        // threads per node-phase block (64 or 256)
     int fused;             // 1: node-centric single-launch iteration (n <= FUSED_MAX_N)
     int nep, nnp;          // partials per edge quantity (dF, e, sup; one per tail node) and per node quantity
+    int edge_par;          // 1: out-edge sums grouped by wave (concurrent edge phase)
     int nrp;               // partials of the residual pass (a, b; one per RES_EDGES edges)
 };
 
@@ -83,9 +84,14 @@ struct Bufs {
 // Launch shape of the two-phase edge kernel: `wpe` waves (of 64 lanes) per tail node, which
 // project its out-edge columns one after another, and `ept` 16-byte vectors per lane.  With
 // wpe == 1 a 256-thread block carries 4 tail nodes, one per wave.
+// par == 1: the tail's out-edges are projected concurrently, one wave per edge in an 8-wave
+// workgroup (a whole column per wave: n <= 64 * ept * 16 / bytes), and the out-edge sums are
+// added per wave and then over the waves in wave order.
 struct EdgeShape {
-    int wpe, ept;
+    int wpe, ept, par;
 };
+// Waves per workgroup of the concurrent edge phase.
+constexpr int EDGE_PAR_WAVES = 8;
 EdgeShape edge_shape_for(int n, int bytes);
 
 // Kernel launchers (defined in mcf_kernels.hip).

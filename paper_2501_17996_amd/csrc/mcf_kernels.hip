@@ -228,36 +228,35 @@ __device__ __forceinline__ double util_traffic(double y, double w, double g)
 
 // Dual proximal operator prox_{beta (-u)^*}(y) of Section 2.3.
 //   log:   (y - sqrt(y^2 + 4 beta w)) / 2, in the cancellation-free form for y > 0;
-//   power: z = -t with t the positive root of t^{c1+2} + y t^{c1+1} = c1 c2.  On
-//          t >= max(-y, 0) that polynomial is increasing and convex, so Newton's
-//          method started right of the root, at max(-y,0) + (c1 c2)^{1/(c1+2)},
-//          decreases monotonically onto it; it stops when a step no longer decreases t.
+//   power: z = -t with t the positive root of h(t) = t^{c1+2} + y t^{c1+1} - c1 c2.  On
+//          t >= a = max(-y, 0) h is increasing and convex, so Newton's method decreases
+//          monotonically onto the root from any point right of it, and one step from a
+//          point left of it (in [a, root)) lands right of it.  The start is the guess
+//          `tg` (the current dual value, -Y_ij, which the new root is close to once the
+//          iteration settles) when it lies in the bracket [a, a + (c1 c2)^{1/(c1+2)}], else
+//          the bracket's right end; iteration stops when a step no longer decreases t.
 template <int UTIL>
-__device__ __forceinline__ double prox_dual(double y, double beta, double w, double g, double c1)
+__device__ __forceinline__ double prox_dual(double y, double beta, double w, double g, double c1, double tg)
 {
     if (UTIL == 0) {
         const double s = sqrt(y * y + 4.0 * beta * w);
         return y <= 0.0 ? 0.5 * (y - s) : -2.0 * beta * w / (y + s);
     }
     const double a = y < 0.0 ? -y : 0.0;
-    if (c1 == 1.0) {  // gamma = 1/2: t^3 + y t^2 - beta w^2 / 4 = 0
-        const double k = beta * w * w * 0.25;
-        double t = a + cbrt(k);
-        for (int it = 0; it < 200; ++it) {
-            const double h = t * t * (t + y) - k;
-            const double hp = t * (3.0 * t + 2.0 * y);
-            const double tn = t - h / hp;
-            if (!(tn < t)) break;
-            t = tn > a ? tn : a;
-        }
-        return -t;
-    }
-    const double k = c1 * beta * (1.0 / g - 1.0) * pow(w * g, 1.0 / (1.0 - g));
-    double t = a + pow(k, 1.0 / (c1 + 2.0));
+    const bool half = c1 == 1.0;  // gamma = 1/2: t^3 + y t^2 - beta w^2 / 4
+    const double k = half ? beta * w * w * 0.25 : c1 * beta * (1.0 / g - 1.0) * pow(w * g, 1.0 / (1.0 - g));
+    auto hval = [&](double t, double &hp) {
+        const double tp = half ? t : pow(t, c1);
+        hp = tp * ((c1 + 2.0) * t + (c1 + 1.0) * y);
+        return tp * t * (t + y) - k;
+    };
+    const double hi = a + (half ? cbrt(k) : pow(k, 1.0 / (c1 + 2.0)));
+    double t = (tg > a && tg < hi) ? tg : hi;
+    double hp;
+    const double h0 = hval(t, hp);
+    if (h0 < 0.0) t = t - h0 / hp;  // from left of the root: one step lands right of it
     for (int it = 0; it < 200; ++it) {
-        const double tp = pow(t, c1);
-        const double h = tp * t * (t + y) - k;
-        const double hp = tp * ((c1 + 2.0) * t + (c1 + 1.0) * y);
+        const double h = hval(t, hp);
         const double tn = t - h / hp;
         if (!(tn < t)) break;
         t = tn > a ? tn : a;
@@ -571,39 +570,217 @@ __global__ __launch_bounds__(WPE == 1 ? 256 : 64 * WPE) void edge_kernel(Consts 
     }
 }
 
+// Concurrent edge phase for columns that fit one wave (n <= 64 * NV * VEC): workgroup =
+// tail node t with EDGE_PAR_WAVES waves; wave w projects the out-edges e0 + w, e0 + w + NW, ...
+// with wave-level reductions only (the search of edge_kernel), so the waves never wait for
+// each other inside the loop.  Each wave adds its new columns into its own out-sum (in the
+// iterate type, in its edge order); the sums are then added over the waves in wave order
+// through LDS into Sout[:,t].  Partials per tail: wave totals added in wave order.
+template <typename T, int NV, bool CHECK, bool PARTIAL>
+__global__ __launch_bounds__(64 * EDGE_PAR_WAVES) void edge_kernel_par(Consts c, Bufs<T> b, PartLayout pl)
+{
+    constexpr int VEC = Vec<T>::N;
+    constexpr int NW = EDGE_PAR_WAVES;
+    constexpr int COL = 64 * NV * VEC;  // entries of one column held by a wave
+    __shared__ __attribute__((aligned(16))) T sol[NW * COL];
+    __shared__ double red[3 * NW];
+    if (b.sc->stop) return;
+    const int tn = xcd_item(blockIdx.x, c.n);
+    if (tn >= c.n) return;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), t = threadIdx.x & 63;
+    const int n = c.n;
+    const long long ld = c.ld;
+    const T ta = (T)b.sc->alpha;
+    const T *yt = b.Y + (long long)tn * ld;
+    const double rho = c.rho, omr = 1.0 - c.rho;
+    const int e0 = b.out_off[tn], e1 = b.out_off[tn + 1];
+    T so[NV][VEC];
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int u = 0; u < VEC; ++u) so[v][u] = T(0);
+    double dF_w = 0.0, e_w = 0.0, sup_w = 0.0;
+    for (int e = e0 + w; e < e1; e += NW) {
+        const T *yh = b.Y + (long long)__builtin_amdgcn_readfirstlane(b.head[e]) * ld;
+        T *f = b.F + (long long)e * ld;
+        const double cap = b.cap[e];
+        const double mu0 = b.mu[e];
+        T fo[NV][VEC], q[NV][VEC], bh[NV][VEC], bt[NV][VEC];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const int i = (v * 64 + t) * VEC;
+            const int ic = i < n ? i : 0;
+            vload_nt(f + ic, fo[v]);
+            vload_nt(yh + ic, bh[v]);
+            vload(yt + ic, bt[v]);
+        }
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const bool ok = (v * 64 + t) * VEC < n;
+#pragma unroll
+            for (int u = 0; u < VEC; ++u) {
+                q[v][u] = ok ? fo[v][u] + ta * (bh[v][u] - bt[v][u]) : T(0);
+                fo[v][u] = ok ? fo[v][u] : T(0);
+            }
+        }
+        auto support_sum = [&](T thr, double &s, int &cnt) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                T part = T(0);
+#pragma unroll
+                for (int u = 0; u < VEC; ++u) {
+                    const bool in = q[v][u] > thr;
+                    if (in) part += q[v][u];
+                    cnt += wave_count(in);
+                }
+                s += (double)part;
+            }
+        };
+        const T thr0 = below(mu0, T(0));
+        double sp = 0.0, sw = 0.0;
+        int cp = 0, cw = 0;
+        support_sum(T(0), sp, cp);
+        support_sum(thr0, sw, cw);
+        wave_sum2(sp, sw);
+        double mu = 0.0;
+        if (sp > cap) {
+            mu = (sp - cap) * b.rcp[cp];
+            int prev = cp;  // mu came from S' = {q > 0}, a superset of {q > mu}
+            if (cw > 0) {
+                const double mw = (sw - cap) * b.rcp[cw];
+                if (mw > mu) {
+                    mu = mw;
+                    prev = mw >= mu0 ? cw : 0x7fffffff;  // {q > mu0} contains {q > mw} only if mw >= mu0
+                }
+            }
+            // each pass counts the support first; only a support that shrank needs its sum
+            for (int pass = 0; pass <= n; ++pass) {
+                const T thr = below(mu, T(0));
+                int cnt = 0;
+#pragma unroll
+                for (int v = 0; v < NV; ++v)
+#pragma unroll
+                    for (int u = 0; u < VEC; ++u) cnt += wave_count(q[v][u] > thr);
+                if (cnt >= prev) break;
+                double s = 0.0;
+                int dummy = 0;
+                support_sum(thr, s, dummy);
+                s = wave_sum(s);
+                mu = (s - cap) * b.rcp[cnt];
+                prev = cnt;
+            }
+        }
+        double dsum = 0.0, esum = 0.0, gmax = -INFINITY;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const int i = (v * 64 + t) * VEC;
+            if (i < n) {
+                T fn[VEC], fhv[VEC], dv[VEC];
+#pragma unroll
+                for (int u = 0; u < VEC; ++u) {
+                    T fov = fo[v][u];
+                    asm volatile("" : "+v"(fov));
+                    const double fod = (double)fov;
+                    const double fh = fmax((double)q[v][u] - mu, 0.0);
+                    fn[u] = (T)(rho * fh + omr * fod);
+                    so[v][u] += fn[u];
+                    if (PARTIAL) {
+                        const double d = (double)fn[u] - fod;
+                        dsum += d * d;
+                    }
+                    if (CHECK) {
+                        fhv[u] = (T)fh;
+                        dv[u] = (T)(fh - (double)q[v][u]);
+                        esum += (double)dv[u] * (double)dv[u];
+                    }
+                }
+                vstore_nt(f + i, fn);
+                if (CHECK) {
+                    vstore_nt(b.Fhat + (long long)e * ld + i, fhv);
+                    vstore_nt(b.D + (long long)e * ld + i, dv);
+#pragma unroll
+                    for (int u = 0; u < VEC; ++u)
+                        if (i + u < n) gmax = fmax(gmax, (double)(bh[v][u] - bt[v][u]));
+                }
+            }
+        }
+        if (PARTIAL) dsum = wave_sum(dsum);
+        if (CHECK) {
+            esum = wave_sum(esum);
+            gmax = wave_max(gmax);
+        }
+        if (t == 0) b.mu[e] = mu;
+        dF_w += dsum;
+        e_w += esum;
+        if (CHECK) sup_w += cap * fmax(gmax, 0.0);  // c_l (max_i (Y A)_il)_+
+    }
+    // out-edge sums over the waves, in wave order
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+        vstore(sol + w * COL + (v * 64 + t) * VEC, so[v]);
+    if (t == 0) {
+        red[w] = dF_w;
+        red[NW + w] = e_w;
+        red[2 * NW + w] = sup_w;
+    }
+    __syncthreads();
+    T *sout = b.Sout + (long long)tn * ld;
+    for (int i = threadIdx.x; i < n; i += 64 * NW) {
+        T acc = T(0);
+#pragma unroll
+        for (int ww = 0; ww < NW; ++ww) acc += sol[ww * COL + i];
+        sout[i] = acc;
+    }
+    if (threadIdx.x == 0) {
+        double a = 0.0, bb = 0.0, cc = 0.0;
+#pragma unroll
+        for (int ww = 0; ww < NW; ++ww) {
+            a += red[ww];
+            bb += red[NW + ww];
+            cc += red[2 * NW + ww];
+        }
+        if (PARTIAL) b.part[pl.dF + tn] = a;
+        if (CHECK) {
+            b.part[pl.e + tn] = bb;
+            b.part[pl.sup + tn] = cc;
+        }
+    }
+}
+
 // -------------------------------------------------------------- node phase
 // Grid (ceil(n/NB), n): thread (x, j) owns entry i of node column j.  Gathers over the
-// CSR edge lists accumulate in FP64 in list order; loads are issued eight edges at a
-// time, the additions stay in list order.
+// CSR edge lists accumulate in FP64 in list order.  Loads are issued sixteen edges at a time
+// and unconditionally (a slot past the list end reloads its last edge and adds nothing), so a
+// node with up to 16 edges in a list costs one round trip to memory.
 template <typename T>
 __device__ __forceinline__ double gather_in(const T *X, const int *in_edge, int i0, int i1, long long ld, int i)
 {
+    constexpr int B = 16;
     double v = 0.0;
-    int k = i0;
-    for (; k + 8 <= i1; k += 8) {
-        T a[8];
+    for (int k = i0; k < i1; k += B) {
+        T a[B];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) a[u] = X[(long long)in_edge[k + u] * ld + i];
+        for (int u = 0; u < B; ++u) a[u] = X[(long long)in_edge[k + u < i1 ? k + u : i1 - 1] * ld + i];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) v += (double)a[u];
+        for (int u = 0; u < B; ++u)
+            if (k + u < i1) v += (double)a[u];
     }
-    for (; k < i1; ++k) v += (double)X[(long long)in_edge[k] * ld + i];
     return v;
 }
 
 template <typename T>
 __device__ __forceinline__ double gather_out(const T *X, int o0, int o1, long long ld, int i)
 {
+    constexpr int B = 16;
     double v = 0.0;
-    int e = o0;
-    for (; e + 8 <= o1; e += 8) {
-        T a[8];
+    for (int e = o0; e < o1; e += B) {
+        T a[B];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) a[u] = X[(long long)(e + u) * ld + i];
+        for (int u = 0; u < B; ++u) a[u] = X[(long long)(e + u < o1 ? e + u : o1 - 1) * ld + i];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) v += (double)a[u];
+        for (int u = 0; u < B; ++u)
+            if (e + u < o1) v += (double)a[u];
     }
-    for (; e < o1; ++e) v += (double)X[(long long)e * ld + i];
     return v;
 }
 
@@ -637,7 +814,7 @@ __global__ __launch_bounds__(NB) void node_kernel(Consts c, Bufs<T> b, PartLayou
         const double v = (2.0 / c.rho) * pn - ((2.0 - c.rho) / c.rho) * po;
         const double y = (double)b.Y[x];
         const double w = (double)b.W[x];
-        const double yhat = (i != j) ? prox_dual<UTIL>(y - beta * v, beta, w, g, c.c1) : 0.0;
+        const double yhat = (i != j) ? prox_dual<UTIL>(y - beta * v, beta, w, g, c.c1, -y) : 0.0;
         const T yn = (T)(c.rho * yhat + (1.0 - c.rho) * y);
         b.Y[x] = yn;
         if (PARTIAL) {
@@ -691,8 +868,8 @@ __global__ __launch_bounds__(NB) void node_kernel(Consts c, Bufs<T> b, PartLayou
     }
 }
 
-// P = F A^T of the current F, with the out-edge sums formed in the iterate type and edge
-// order as the edge phase forms them, so that P is the one an uninterrupted run would hold.
+// P = F A^T of the current F, with the out-edge sums formed in the iterate type and in the
+// order the edge phase forms them, so that P is the one an uninterrupted run would hold.
 template <typename T, int NB>
 __global__ __launch_bounds__(NB) void p_from_f_kernel(Consts c, Bufs<T> b)
 {
@@ -700,7 +877,17 @@ __global__ __launch_bounds__(NB) void p_from_f_kernel(Consts c, Bufs<T> b)
     const int i = blockIdx.x * NB + threadIdx.x;
     if (i >= c.n) return;
     T so = T(0);
-    for (int e = b.out_off[j]; e < b.out_off[j + 1]; ++e) so += b.F[(long long)e * c.ld + i];
+    const int e0 = b.out_off[j], e1 = b.out_off[j + 1];
+    if (c.edge_par) {
+        // per wave of the concurrent edge phase (edges e0 + w, e0 + w + NW, ...), then over the waves
+        for (int w = 0; w < EDGE_PAR_WAVES; ++w) {
+            T sw = T(0);
+            for (int e = e0 + w; e < e1; e += EDGE_PAR_WAVES) sw += b.F[(long long)e * c.ld + i];
+            so += sw;
+        }
+    } else {
+        for (int e = e0; e < e1; ++e) so += b.F[(long long)e * c.ld + i];
+    }
     const long long x = (long long)j * c.ld + i;
     b.P[x] = (T)p_entry<T>(b.F, b.in_edge, b.in_off[j], b.in_off[j + 1], so, c.ld, i);
 }
@@ -922,7 +1109,7 @@ __device__ __forceinline__ void fused_body(const Consts &c, const Bufs<T> &b, co
         }
         const long long x = (long long)j * ld + i;
         const double y = (double)yrow[r], w = (double)wrow[r];
-        const double yhat = (i != j) ? prox_dual<UTIL>(y - beta * v, beta, w, g, c.c1) : 0.0;
+        const double yhat = (i != j) ? prox_dual<UTIL>(y - beta * v, beta, w, g, c.c1, -y) : 0.0;
         const T yn = (T)(rho * yhat + omr * y);
         Yn[x] = yn;
         if (PARTIAL) {
@@ -1276,26 +1463,29 @@ __global__ void pool_gather_kernel(const SlotDesc<T> *slots, int nslots, DevScal
 // `bytes`-byte entries: enough lanes to cover n, with a 256-thread block (four waves) for
 // large n so that several blocks stay resident on a CU, and 512 threads for the largest
 // FP64 columns to keep the per-lane register count bounded.
-// Tail-grouped edge phase: each lane holds 2 * NV * VEC iterate values (F and q) and NV * VEC
-// FP64 out-edge sums; eight waves per tail node from n = 4096 on (FP32) keep that near
-// 100 VGPRs, sixteen for FP64 beyond n = 8192.
+// Edge phase shapes.  Up to n = 64 * 8 * VEC (2048 FP32, 1024 FP64) a column fits one wave with
+// at most 8 vectors per lane, and the tail's out-edges are projected concurrently (par).  Beyond
+// that the tail's waves share each column: each lane holds 2 * NV * VEC iterate values (F and
+// q), with the out-edge sums in LDS; eight waves per tail node from n = 4096 on (FP32) keep that
+// near 100 VGPRs, sixteen for FP64 beyond n = 8192.
 EdgeShape edge_shape_for(int n, int bytes)
 {
     const int vec = 16 / bytes;
-    if (n <= 64 * vec) return {1, 1};
-    if (n <= 128 * vec) return {1, 2};
+    const int nvp[] = {1, 2, 4, 8};
+    for (int nv : nvp)
+        if (n <= 64 * vec * nv) return {1, nv, 1};
     const int nv4[] = {1, 2, 4};
     for (int nv : nv4)
-        if (n <= 256 * vec * nv) return {4, nv};
+        if (n <= 256 * vec * nv) return {4, nv, 0};
     if (bytes == 4) {
         const int nv8[] = {3, 4, 6, 8};
         for (int nv : nv8)
-            if (n <= 512 * vec * nv) return {8, nv};
-        return {8, 8};
+            if (n <= 512 * vec * nv) return {8, nv, 0};
+        return {8, 8, 0};
     }
-    if (n <= 512 * vec * 4) return {8, 4};
-    if (n <= 512 * vec * 8) return {8, 8};
-    return {16, 8};
+    if (n <= 512 * vec * 4) return {8, 4, 0};
+    if (n <= 512 * vec * 8) return {8, 8, 0};
+    return {16, 8, 0};
 }
 
 int node_block_for(int n) { return n <= 512 ? 64 : 256; }
@@ -1320,14 +1510,34 @@ static void edge_go(const Consts &c, const Bufs<T> &b, const PartLayout &pl, boo
         hipExtLaunchKernelGGL((edge_kernel<T, WPE, NV, false, false>), grid, block, 0, st, e0, e1, 0, c, b, pl);
 }
 
+template <typename T, int NV>
+static void edge_par_go(const Consts &c, const Bufs<T> &b, const PartLayout &pl, bool check, bool partial,
+                        hipStream_t st, hipEvent_t e0, hipEvent_t e1)
+{
+    const dim3 grid(xcd_grid(c.n)), block(64 * EDGE_PAR_WAVES);
+    if (check)
+        hipExtLaunchKernelGGL((edge_kernel_par<T, NV, true, true>), grid, block, 0, st, e0, e1, 0, c, b, pl);
+    else if (partial)
+        hipExtLaunchKernelGGL((edge_kernel_par<T, NV, false, true>), grid, block, 0, st, e0, e1, 0, c, b, pl);
+    else
+        hipExtLaunchKernelGGL((edge_kernel_par<T, NV, false, false>), grid, block, 0, st, e0, e1, 0, c, b, pl);
+}
+
 template <typename T>
 hipError_t launch_edge(const Consts &c, const Bufs<T> &b, const PartLayout &pl, EdgeShape sh, bool check,
                        bool partial, hipStream_t st, hipEvent_t e0, hipEvent_t e1)
 {
+    if (sh.par) {
+        switch (sh.ept) {
+        case 1: edge_par_go<T, 1>(c, b, pl, check, partial, st, e0, e1); return hipGetLastError();
+        case 2: edge_par_go<T, 2>(c, b, pl, check, partial, st, e0, e1); return hipGetLastError();
+        case 4: edge_par_go<T, 4>(c, b, pl, check, partial, st, e0, e1); return hipGetLastError();
+        case 8: edge_par_go<T, 8>(c, b, pl, check, partial, st, e0, e1); return hipGetLastError();
+        default: return hipErrorInvalidValue;
+        }
+    }
 #define MCF_EDGE_CASE(W, V) \
     if (sh.wpe == W && sh.ept == V) { edge_go<T, W, V>(c, b, pl, check, partial, st, e0, e1); return hipGetLastError(); }
-    MCF_EDGE_CASE(1, 1)
-    MCF_EDGE_CASE(1, 2)
     MCF_EDGE_CASE(4, 1)
     MCF_EDGE_CASE(4, 2)
     MCF_EDGE_CASE(4, 4)

@@ -582,6 +582,7 @@ int mcf_create(int32_t n, int32_t m, const int32_t *tail, const int32_t *head, c
     c.nblk_node = node_blocks(n);
     c.node_block = node_block_for(n);
     c.fused = fused ? 1 : 0;
+    c.edge_par = s->sh.par;
     c.nep = n;  // edge quantities are added per tail node
     c.nrp = (m + RES_EDGES - 1) / RES_EDGES;
     c.nnp = fused ? n : c.nblk_node;
@@ -800,7 +801,7 @@ int mcf_layout(const mcf_solver *s, int32_t *ld, int32_t *edge_block, int32_t *e
 {
     if (!s) return MCF_E_ARG;
     if (ld) *ld = (int32_t)s->ld;
-    if (edge_block) *edge_block = 64 * s->sh.wpe;
+    if (edge_block) *edge_block = 64 * (s->sh.par ? EDGE_PAR_WAVES : s->sh.wpe);
     if (edge_ept) *edge_ept = s->sh.ept * (s->precision == MCF_FP32 ? 4 : 2);
     if (kernel_mode) *kernel_mode = s->c.fused ? MCF_KERNELS_FUSED : MCF_KERNELS_TWO_PHASE;
     return MCF_OK;
