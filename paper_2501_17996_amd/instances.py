@@ -201,3 +201,31 @@ def knn_geometric(n: int, q: int, seed: int) -> Instance:
 
 
 CONFIGS = {"c1": config1, "c2": config2, "c3": config3, "c4": config4}
+
+
+def with_parallel_edges(inst: Instance, count: int, seed: int) -> Instance:
+    """A copy of `inst` with `count` of its edges duplicated (same tail and head), each copy with
+    a capacity of its own drawn from U[0.5, 2]; the copies are appended after the edges of `inst`."""
+    rng = _rng(seed)
+    pick = rng.choice(inst.m, size=count, replace=False)
+    tail = np.concatenate([inst.tail, inst.tail[pick]]).astype(np.int32)
+    head = np.concatenate([inst.head, inst.head[pick]]).astype(np.int32)
+    cap = np.concatenate([inst.cap, rng.uniform(0.5, 2.0, size=count)])
+    return Instance(inst.n, tail, head, cap, inst.utility, inst.gamma, inst.w.copy(),
+                    name=f"{inst.name}+par{count}", seed=seed, meta={"parallel_of": pick.tolist()})
+
+
+def hub_instance(n: int, seed: int, utility: int = UTIL_LOG, gamma: float = 0.5) -> Instance:
+    """Ring over nodes 1..n-1 plus a hub, node 0, joined to every other node in both directions:
+    the hub has 2(n-1) incident edges (a skewed degree distribution), every other node four."""
+    rng = _rng(seed)
+    others = np.arange(1, n, dtype=np.int32)
+    ring_t = others
+    ring_h = np.concatenate([others[1:], others[:1]])
+    hub = np.zeros(n - 1, dtype=np.int32)
+    tail = np.concatenate([ring_t, hub, others]).astype(np.int32)
+    head = np.concatenate([ring_h, others, hub]).astype(np.int32)
+    cap = rng.uniform(0.5, 2.0, size=tail.shape[0])
+    w = _weights(n, 0.5, 1.5, rng)
+    g = gamma if utility == UTIL_POWER else 0.0
+    return Instance(n, tail, head, cap, utility, g, w, name=f"hub{n}", seed=seed)

@@ -238,6 +238,37 @@ def test_knn_frozen_primal_weight_converges(M):
     print(f"knn n=100 frozen omega: converged at {k}, rel_gap {st['rel_gap']:.2e}")
 
 
+def _checkpoints(M, inst, mode, ks, precision=0):
+    S = gpu_solver(M, inst, kernel_mode=mode, precision=precision)
+    O = oracle.OracleSolver(inst, threads=THREADS)
+    done = 0
+    for k in ks:
+        S.run(k - done)
+        O.run(k - done - 1, check=False)
+        mo = O.step(check=True)
+        done = k
+        assert_state_close(S, O, what=f"{inst.name} mode {mode} k={k}")
+        assert_metrics_close(S.status(), mo, what=f"{inst.name} mode {mode} k {k}")
+    return S
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_parallel_edges_trajectory(M, mode):
+    """Parallel edges (allowed by the boundary): each copy is its own column of F, and each
+    counts in d_max."""
+    inst = I.with_parallel_edges(I.ring_instance(150, 5, seed=8), 60, seed=9)
+    _checkpoints(M, inst, mode, (1, 2, 40, 150))
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_hub_node_trajectory(M, mode):
+    """A hub with 2(n-1) = 798 incident edges: in the fused iteration its incidence list spans
+    several LDS chunks, in the two-phase one its 399 out-edges cycle through the waves of one
+    workgroup and its in-gather runs 25 batches."""
+    inst = I.hub_instance(400, 1)
+    _checkpoints(M, inst, mode, (1, 2, 30, 100))
+
+
 def test_c3_fp64_first_iterations(M):
     inst = I.config3(0)
     S = gpu_solver(M, inst)

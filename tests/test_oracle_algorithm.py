@@ -521,3 +521,27 @@ def test_trajectory_regression_golden(orc):
                     assert not math.isfinite(M[key])
                 else:
                     assert M[key] == pytest.approx(exp, rel=1e-12, abs=1e-300)
+
+
+# ------------------------------------------------------------- parallel edges
+def test_parallel_edges_equal_merged_capacity(orc):
+    """Two parallel edges with capacities c1, c2 carry exactly the flows one edge of capacity
+    c1 + c2 could (the projection acts per column, the constraint sets add), so the optimal
+    traffic of (e-prob), which is unique, must be the same for both graphs.  The two runs have
+    different incidence matrices, d_max and eta, hence different trajectories."""
+    base = I.ring_instance(8, 3, seed=21)
+    dup = I.with_parallel_edges(base, 6, seed=4)
+    picks = dup.meta["parallel_of"]
+    merged_cap = base.cap.copy()
+    for q, l in enumerate(picks):
+        merged_cap[l] += dup.cap[base.m + q]
+    merged = I.Instance(base.n, base.tail, base.head, merged_cap, base.utility, base.gamma, base.w,
+                        name="merged")
+    out = []
+    for inst in (dup, merged):
+        s = orc.OracleSolver(inst)
+        assert s.solve(1e-9, max_iter=200000, check_every=10) == "converged"
+        _, T, _ = _last_math(s, inst)
+        out.append((T, s.metrics()["primal_obj"]))
+    np.testing.assert_allclose(out[0][0], out[1][0], rtol=1e-6, atol=1e-8)
+    assert out[0][1] == pytest.approx(out[1][1], rel=1e-9)
