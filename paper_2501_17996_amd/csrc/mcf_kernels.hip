@@ -85,6 +85,16 @@ __device__ __forceinline__ void wave_sum2(double &x, double &y)
     y = ((lane_f64(y, 0) + lane_f64(y, 16)) + lane_f64(y, 32)) + lane_f64(y, 48);
 }
 
+// 1/k from the per-instance table (k = 1..n), read through the constant address space with a
+// wave-uniform k: a scalar load.  A vector load here would make the search wait for every
+// vector memory operation still in flight (the next edge's column loads, the stores just
+// issued), since those waits count all of them.
+__device__ __forceinline__ double rcp_of(const double *tab, int k)
+{
+    typedef const __attribute__((address_space(4))) double cdouble;
+    return ((cdouble *)tab)[__builtin_amdgcn_readfirstlane(k)];
+}
+
 // Number of lanes of the wave for which p holds (wave-uniform): a ballot, no reduction chain.
 __device__ __forceinline__ int wave_count(bool p)
 {
@@ -471,10 +481,10 @@ __global__ __launch_bounds__(WPE == 1 ? 256 : 64 * WPE) void edge_kernel(Consts 
         }
         double mu = 0.0;
         if (sp > cap) {
-            mu = (sp - cap) * b.rcp[cp];
+            mu = (sp - cap) * rcp_of(b.rcp, cp);
             int prev = cp;  // mu came from S' = {q > 0}, a superset of {q > mu}
             if (cw > 0) {
-                const double mw = (sw - cap) * b.rcp[cw];
+                const double mw = (sw - cap) * rcp_of(b.rcp, cw);
                 if (mw > mu) {
                     mu = mw;
                     prev = mw >= mu0 ? cw : 0x7fffffff;  // {q > mu0} contains {q > mw} only if mw >= mu0
@@ -503,7 +513,7 @@ __global__ __launch_bounds__(WPE == 1 ? 256 : 64 * WPE) void edge_kernel(Consts 
                     group_combine<WPE, 1>(g, lds);
                     s = g[0];
                 }
-                mu = (s - cap) * b.rcp[cnt];
+                mu = (s - cap) * rcp_of(b.rcp, cnt);
                 prev = cnt;
             }
         }
@@ -644,10 +654,10 @@ __global__ __launch_bounds__(64 * EDGE_PAR_WAVES) void edge_kernel_par(Consts c,
         wave_sum2(sp, sw);
         double mu = 0.0;
         if (sp > cap) {
-            mu = (sp - cap) * b.rcp[cp];
+            mu = (sp - cap) * rcp_of(b.rcp, cp);
             int prev = cp;  // mu came from S' = {q > 0}, a superset of {q > mu}
             if (cw > 0) {
-                const double mw = (sw - cap) * b.rcp[cw];
+                const double mw = (sw - cap) * rcp_of(b.rcp, cw);
                 if (mw > mu) {
                     mu = mw;
                     prev = mw >= mu0 ? cw : 0x7fffffff;  // {q > mu0} contains {q > mw} only if mw >= mu0
@@ -666,7 +676,7 @@ __global__ __launch_bounds__(64 * EDGE_PAR_WAVES) void edge_kernel_par(Consts c,
                 int dummy = 0;
                 support_sum(thr, s, dummy);
                 s = wave_sum(s);
-                mu = (s - cap) * b.rcp[cnt];
+                mu = (s - cap) * rcp_of(b.rcp, cnt);
                 prev = cnt;
             }
         }
@@ -1021,10 +1031,10 @@ __device__ __forceinline__ void fused_body(const Consts &c, const Bufs<T> &b, co
         wave_sum2(sp, sw);
         double mu = 0.0;
         if (sp > cap) {
-            mu = (sp - cap) * b.rcp[cp];
+            mu = (sp - cap) * rcp_of(b.rcp, cp);
             int prev = cp;
             if (cw > 0) {
-                const double mw = (sw - cap) * b.rcp[cw];
+                const double mw = (sw - cap) * rcp_of(b.rcp, cw);
                 if (mw > mu) {
                     mu = mw;
                     prev = mw >= mu0 ? cw : 0x7fffffff;
@@ -1042,7 +1052,7 @@ __device__ __forceinline__ void fused_body(const Consts &c, const Bufs<T> &b, co
                 for (int jj = 0; jj < EPT; ++jj)
                     if (q[jj] > thr) ps += q[jj];
                 const double s = wave_sum((double)ps);
-                mu = (s - cap) * b.rcp[cnt];
+                mu = (s - cap) * rcp_of(b.rcp, cnt);
                 prev = cnt;
             }
         }
