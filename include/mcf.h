@@ -38,7 +38,14 @@ extern "C" {
 
 typedef struct mcf_solver mcf_solver; /* opaque; owns its device buffers */
 
-enum { MCF_UTIL_LOG = 0, MCF_UTIL_POWER = 1 };            /* u = w log s  |  u = w s^gamma (Section 1.1) */
+/* Utilities (Section 1.1 allows any strictly concave increasing u on s > 0; Section 2.3 solves
+ * the one-dimensional dual prox for it in general):
+ *   LOG    u = w log s;
+ *   POWER  u = w s^gamma, gamma in (0, 1);
+ *   ALPHA  the alpha-fair family u = w s^(1-alpha) / (1-alpha), 0 < alpha <= 16, alpha != 1
+ *          (alpha > 1 gives negative utilities that penalise small traffic more; LOG is its
+ *          limit alpha -> 1, and alpha = 1 - gamma with weight w gamma is POWER). */
+enum { MCF_UTIL_LOG = 0, MCF_UTIL_POWER = 1, MCF_UTIL_ALPHA = 2 };
 enum { MCF_FP64 = 0, MCF_FP32 = 1 };                     /* precision of F, Y; reductions are always FP64 */
 enum { MCF_STOP_REL_KKT = 0, MCF_STOP_PAPER = 1 };       /* rel_kkt <= tol  |  r^k < n m tol (Algorithm 2.1) */
 enum { MCF_OK = 0, MCF_E_ARG = -1, MCF_E_GRAPH = -2, MCF_E_NOMEM = -3, MCF_E_DEVICE = -4, MCF_E_STATE = -5 };
@@ -103,7 +110,8 @@ size_t mcf_workspace_bytes(int32_t n, int32_t m, int32_t precision);
  *   n, m       nodes (2 <= n <= 16384) and edges (m >= 1);
  *   tail, head m edge endpoints in [0, n), tail != head (parallel edges allowed);
  *   cap        m capacities c_l > 0 (Section 1.1);
- *   utility    MCF_UTIL_LOG or MCF_UTIL_POWER; gamma in (0, 1) for POWER (ignored for LOG);
+ *   utility    MCF_UTIL_LOG, MCF_UTIL_POWER or MCF_UTIL_ALPHA; gamma is the power utility's gamma
+ *              (0 < gamma < 1) or the alpha-fair alpha (0 < alpha <= 16, alpha != 1); ignored for LOG;
  *   w          n*n weights, w[j*n+i] > 0 for i != j (diagonal ignored);
  *   opt        options or NULL for the defaults.
  * Errors: MCF_E_ARG for any range/positivity/NULL violation or tol <= 0; MCF_E_GRAPH if the

@@ -71,6 +71,8 @@ def lib():
         L.orc_prox_log.argtypes = [_d, _d, _d]
         L.orc_prox_power.restype = _d
         L.orc_prox_power.argtypes = [_d, _d, _d, _d]
+        L.orc_prox_alpha.restype = _d
+        L.orc_prox_alpha.argtypes = [_d, _d, _d, _d]
         L.orc_project.restype = _d
         L.orc_project.argtypes = [_i32, _dp, _d, _dp]
         L.orc_eta.restype = _d
@@ -104,6 +106,10 @@ def prox_log(y: float, beta: float, w: float) -> float:
 
 def prox_power(y: float, beta: float, w: float, gamma: float) -> float:
     return lib().orc_prox_power(float(y), float(beta), float(w), float(gamma))
+
+
+def prox_alpha(y: float, beta: float, w: float, alpha: float) -> float:
+    return lib().orc_prox_alpha(float(y), float(beta), float(w), float(alpha))
 
 
 def project(q, c: float):

@@ -22,7 +22,11 @@
  * Readings taken where the paper is silent (each is listed in the design notes):
  *   - the relative KKT residual, the Y that pairs with F^ in the gap (Y^k),
  *     k = 0 counting as a multiple of k_adapt, tau absolute, the stable form of
- *     the log prox for y > 0, bisection for the power prox, d_i = in+out degree.
+ *     the log prox for y > 0, bisection for the power prox, d_i = in+out degree;
+ *   - the alpha-fair family u(s) = w s^{1-alpha}/(1-alpha), alpha > 0, alpha != 1, as the
+ *     general strictly concave increasing utility of Section 1.1 whose one-dimensional
+ *     prox Section 2.3 leaves to the general case (log is its limit alpha -> 1, the
+ *     power utility w s^gamma is alpha = 1 - gamma with weight w gamma).
  *
  * Layout: F is n x m with F[l*n + i] the flow on edge l destined to node i.
  * Y, T, W are n x n with X[j*n + i] holding entry (i, j); w[j*n+i] weights the
@@ -38,6 +42,7 @@
 
 #define ORC_UTIL_LOG 0
 #define ORC_UTIL_POWER 1
+#define ORC_UTIL_ALPHA 2
 
 /* metric slots filled by orc_get_metrics */
 enum {
@@ -66,33 +71,42 @@ typedef struct orc_solver {
 } orc_solver;
 
 /* ------------------------------------------------------------------ utilities */
-/* Section 1.1 "Network utility": u(s) = w log s, or u(s) = w s^gamma. */
+/* Section 1.1 "Network utility": u(s) = w log s, u(s) = w s^gamma, or the alpha-fair
+ * u(s) = w s^{1-a}/(1-a) (the parameter g is gamma for the power utility, a for alpha-fair). */
 static double util_u(int32_t ut, double g, double w, double s)
 {
-    return ut == ORC_UTIL_LOG ? w * log(s) : w * pow(s, g);
+    if (ut == ORC_UTIL_LOG) return w * log(s);
+    if (ut == ORC_UTIL_POWER) return w * pow(s, g);
+    return w * pow(s, 1.0 - g) / (1.0 - g);
 }
 
 /* derivative u'(s), used for U' in the residual (Section 1.2, "Optimality condition") */
 static double util_du(int32_t ut, double g, double w, double s)
 {
-    return ut == ORC_UTIL_LOG ? w / s : w * g * pow(s, g - 1.0);
+    if (ut == ORC_UTIL_LOG) return w / s;
+    if (ut == ORC_UTIL_POWER) return w * g * pow(s, g - 1.0);
+    return w * pow(s, -g);
+}
+
+/* the maximizer s of y s + u(s): the traffic that dual price y asks for (y < 0), from
+ * u'(s) = -y */
+static double util_traffic_of_price(int32_t ut, double g, double w, double y)
+{
+    if (ut == ORC_UTIL_LOG) return w / (-y);
+    if (ut == ORC_UTIL_POWER) return pow(w * g / (-y), 1.0 / (1.0 - g));
+    return pow(w / (-y), 1.0 / g);
 }
 
 /* conjugate (-u)^*(y) = sup_s ( y s + u(s) ), finite only for y < 0 (used in (e-L)).
- * log:   -w + w log w - w log(-y)
- * power: (1/g - 1) (w g)^{1/(1-g)} (-y)^{-g/(1-g)} */
+ * log:         -w + w log w - w log(-y)
+ * power:       (1/g - 1) (w g)^{1/(1-g)} (-y)^{-g/(1-g)}
+ * alpha-fair:  at the maximizer s, w s^{1-a} = -y s, so the value is (-y) s a / (1 - a) */
 static double util_conj(int32_t ut, double g, double w, double y)
 {
     if (!(y < 0.0)) return INFINITY;
     if (ut == ORC_UTIL_LOG) return -w + w * log(w) - w * log(-y);
-    return (1.0 / g - 1.0) * pow(w * g, 1.0 / (1.0 - g)) * pow(-y, -g / (1.0 - g));
-}
-
-/* the maximizer s of y s + u(s): the traffic that dual price y asks for (y < 0) */
-static double util_traffic_of_price(int32_t ut, double g, double w, double y)
-{
-    if (ut == ORC_UTIL_LOG) return w / (-y);
-    return pow(w * g / (-y), 1.0 / (1.0 - g));
+    if (ut == ORC_UTIL_POWER) return (1.0 / g - 1.0) * pow(w * g, 1.0 / (1.0 - g)) * pow(-y, -g / (1.0 - g));
+    return (-y) * util_traffic_of_price(ut, g, w, y) * g / (1.0 - g);
 }
 
 /* ---------------------------------------------------------- proximal operators */
@@ -115,11 +129,10 @@ static double power_poly(double t, double y, double c1, double k)
     return pow(t, c1 + 1.0) * (t + y) - k;
 }
 
-double orc_prox_power(double y, double beta, double w, double g)
+/* the root t > a = max(-y, 0) of t^{c1+1} (t + y) = k (k > 0), by bisection on
+ * [a, a + k^{1/(c1+2)}] down to adjacent doubles */
+static double bisect_root(double y, double c1, double k)
 {
-    double c1 = g / (1.0 - g);
-    double c2 = beta * (1.0 / g - 1.0) * pow(w * g, 1.0 / (1.0 - g));
-    double k = c1 * c2;
     double a = y < 0.0 ? -y : 0.0;
     double lo = a, hi = a + pow(k, 1.0 / (c1 + 2.0));
     int guard = 0;
@@ -129,13 +142,30 @@ double orc_prox_power(double y, double beta, double w, double g)
         if (!(mid > lo && mid < hi)) break;
         if (power_poly(mid, y, c1, k) < 0.0) lo = mid; else hi = mid;
     }
-    double t = fabs(power_poly(lo, y, c1, k)) < fabs(power_poly(hi, y, c1, k)) ? lo : hi;
-    return -t;
+    return fabs(power_poly(lo, y, c1, k)) < fabs(power_poly(hi, y, c1, k)) ? lo : hi;
+}
+
+double orc_prox_power(double y, double beta, double w, double g)
+{
+    double c1 = g / (1.0 - g);
+    double c2 = beta * (1.0 / g - 1.0) * pow(w * g, 1.0 / (1.0 - g));
+    return -bisect_root(y, c1, c1 * c2);
+}
+
+/* Alpha-fair utility u(s) = w s^{1-a}/(1-a): the optimality condition of the prox,
+ * z + beta s(z) = y with the traffic s(z) = (w/(-z))^{1/a} of price z < 0, reads with
+ * t = -z and p = 1/a:  t^{p+1} + y t^p = beta w^p.  Same bisection, with c1 = p - 1. */
+double orc_prox_alpha(double y, double beta, double w, double a)
+{
+    double p = 1.0 / a;
+    return -bisect_root(y, p - 1.0, beta * pow(w, p));
 }
 
 static double prox_dual(int32_t ut, double g, double y, double beta, double w)
 {
-    return ut == ORC_UTIL_LOG ? orc_prox_log(y, beta, w) : orc_prox_power(y, beta, w, g);
+    if (ut == ORC_UTIL_LOG) return orc_prox_log(y, beta, w);
+    if (ut == ORC_UTIL_POWER) return orc_prox_power(y, beta, w, g);
+    return orc_prox_alpha(y, beta, w, g);
 }
 
 /* ------------------------------------------------------ projection onto S_l */

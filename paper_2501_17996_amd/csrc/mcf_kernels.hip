@@ -212,28 +212,37 @@ __device__ __forceinline__ double group_max(double x, double *lds)
 }
 
 // --------------------------------------------------------------- utilities
-// Section 1.1: u(s) = w log s (log) or w s^gamma (power); u' for U' = u'(T);
-// the conjugate (-u)^*(y) and the traffic s(y) maximizing y s + u(s), both for y < 0.
+// Section 1.1: u(s) = w log s (UTIL 0), w s^g (UTIL 1, power, g = gamma) or the alpha-fair
+// w s^{1-g} / (1-g) (UTIL 2, g = alpha); u' for U' = u'(T); the traffic s(y) maximizing
+// y s + u(s), from u'(s) = -y, and the conjugate (-u)^*(y) = y s(y) + u(s(y)), both for y < 0.
+// For the alpha-fair utility w s^{1-g} = -y s at s = s(y), so the conjugate is (-y) s g/(1-g).
 template <int UTIL>
 __device__ __forceinline__ double util_u(double s, double w, double g)
 {
-    return UTIL == 0 ? w * log(s) : w * pow(s, g);
+    if (UTIL == 0) return w * log(s);
+    if (UTIL == 1) return w * pow(s, g);
+    return w * pow(s, 1.0 - g) / (1.0 - g);
 }
 template <int UTIL>
 __device__ __forceinline__ double util_du(double s, double w, double g)
 {
-    return UTIL == 0 ? w / s : w * g * pow(s, g - 1.0);
+    if (UTIL == 0) return w / s;
+    if (UTIL == 1) return w * g * pow(s, g - 1.0);
+    return w * pow(s, -g);
+}
+template <int UTIL>
+__device__ __forceinline__ double util_traffic(double y, double w, double g)
+{
+    if (UTIL == 0) return w / (-y);
+    if (UTIL == 1) return pow(w * g / (-y), 1.0 / (1.0 - g));
+    return pow(w / (-y), 1.0 / g);
 }
 template <int UTIL>
 __device__ __forceinline__ double util_conj(double y, double w, double g)
 {
     if (UTIL == 0) return -w + w * log(w) - w * log(-y);
-    return (1.0 / g - 1.0) * pow(w * g, 1.0 / (1.0 - g)) * pow(-y, -g / (1.0 - g));
-}
-template <int UTIL>
-__device__ __forceinline__ double util_traffic(double y, double w, double g)
-{
-    return UTIL == 0 ? w / (-y) : pow(w * g / (-y), 1.0 / (1.0 - g));
+    if (UTIL == 1) return (1.0 / g - 1.0) * pow(w * g, 1.0 / (1.0 - g)) * pow(-y, -g / (1.0 - g));
+    return (-y) * util_traffic<2>(y, w, g) * g / (1.0 - g);
 }
 
 // Dual proximal operator prox_{beta (-u)^*}(y) of Section 2.3.
@@ -245,6 +254,34 @@ __device__ __forceinline__ double util_traffic(double y, double w, double g)
 //          `tg` (the current dual value, -Y_ij, which the new root is close to once the
 //          iteration settles) when it lies in the bracket [a, a + (c1 c2)^{1/(c1+2)}], else
 //          the bracket's right end; iteration stops when a step no longer decreases t.
+//   alpha-fair: the optimality condition z + beta s(z) = y gives, with t = -z and p = 1/alpha
+//          (passed as c1), h(t) = t^p (t + y) - beta w^p = 0 on the same kind of bracket.  For
+//          alpha > 1 (p < 1) and y > 0, h is concave near 0, where a Newton step from the right
+//          can leave the bracket; so the bracket [lo, hi] is kept by the sign of h and a step
+//          that leaves it is replaced by bisection (safeguarded Newton).
+template <int UTIL>
+__device__ __forceinline__ double prox_alpha(double y, double beta, double w, double p, double tg)
+{
+    const double a = y < 0.0 ? -y : 0.0;
+    const double k = beta * pow(w, p);
+    double lo = a, hi = a + pow(k, 1.0 / (p + 1.0));  // h(lo) < 0 <= h(hi)
+    double t = (tg > lo && tg < hi) ? tg : hi;
+    for (int it = 0; it < 200; ++it) {
+        const double tq = pow(t, p - 1.0);
+        const double h = tq * t * (t + y) - k;
+        if (h == 0.0) break;
+        if (h < 0.0) lo = t;
+        else hi = t;
+        const double mid = 0.5 * (lo + hi);
+        if (!(mid > lo && mid < hi)) break;  // the bracket is two adjacent doubles
+        double tn = t - h / (tq * ((p + 1.0) * t + p * y));
+        if (!(tn > lo && tn < hi)) tn = mid;
+        if (tn == t) break;
+        t = tn;
+    }
+    return -t;
+}
+
 template <int UTIL>
 __device__ __forceinline__ double prox_dual(double y, double beta, double w, double g, double c1, double tg)
 {
@@ -252,6 +289,7 @@ __device__ __forceinline__ double prox_dual(double y, double beta, double w, dou
         const double s = sqrt(y * y + 4.0 * beta * w);
         return y <= 0.0 ? 0.5 * (y - s) : -2.0 * beta * w / (y + s);
     }
+    if (UTIL == 2) return prox_alpha<UTIL>(y, beta, w, c1, tg);
     const double a = y < 0.0 ? -y : 0.0;
     const bool half = c1 == 1.0;  // gamma = 1/2: t^3 + y t^2 - beta w^2 / 4
     const double k = half ? beta * w * w * 0.25 : c1 * beta * (1.0 / g - 1.0) * pow(w * g, 1.0 / (1.0 - g));
@@ -1412,7 +1450,8 @@ __device__ __forceinline__ void pool_util(const SlotDesc<T> &d, int parity, int 
                                           double *red, int2 *incs)
 {
     if (d.c.utility == 0) pool_body<T, EPT, 0, CHECK>(d, parity, j, partial, vsh, red, incs);
-    else pool_body<T, EPT, 1, CHECK>(d, parity, j, partial, vsh, red, incs);
+    else if (d.c.utility == 1) pool_body<T, EPT, 1, CHECK>(d, parity, j, partial, vsh, red, incs);
+    else pool_body<T, EPT, 2, CHECK>(d, parity, j, partial, vsh, red, incs);
 }
 
 template <typename T, bool CHECK>
@@ -1579,10 +1618,12 @@ hipError_t launch_node(const Consts &c, const Bufs<T> &b, const PartLayout &pl, 
 {
     if (c.node_block == 64) {
         if (c.utility == 0) node_go<T, 64, 0>(c, b, pl, check, partial, st, e0, e1);
-        else node_go<T, 64, 1>(c, b, pl, check, partial, st, e0, e1);
+        else if (c.utility == 1) node_go<T, 64, 1>(c, b, pl, check, partial, st, e0, e1);
+        else node_go<T, 64, 2>(c, b, pl, check, partial, st, e0, e1);
     } else {
         if (c.utility == 0) node_go<T, 256, 0>(c, b, pl, check, partial, st, e0, e1);
-        else node_go<T, 256, 1>(c, b, pl, check, partial, st, e0, e1);
+        else if (c.utility == 1) node_go<T, 256, 1>(c, b, pl, check, partial, st, e0, e1);
+        else node_go<T, 256, 2>(c, b, pl, check, partial, st, e0, e1);
     }
     return hipGetLastError();
 }
@@ -1612,7 +1653,8 @@ hipError_t launch_fused(const Consts &c, const Bufs<T> &b, const PartLayout &pl,
 #define MCF_FUSED_CASE(E)                                                  \
     if (c.n <= 64 * E) {                                                   \
         if (c.utility == 0) fused_go<T, E, 0>(c, b, pl, parity, check, partial, st, e0, e1); \
-        else fused_go<T, E, 1>(c, b, pl, parity, check, partial, st, e0, e1); \
+        else if (c.utility == 1) fused_go<T, E, 1>(c, b, pl, parity, check, partial, st, e0, e1); \
+        else fused_go<T, E, 2>(c, b, pl, parity, check, partial, st, e0, e1); \
         return hipGetLastError();                                          \
     }
     MCF_FUSED_CASE(1)

@@ -534,8 +534,9 @@ int mcf_create(int32_t n, int32_t m, const int32_t *tail, const int32_t *head, c
     if (opt) o = *opt;
     else mcf_options_default(&o);
     if (n < 2 || n > MAX_N || m < 1 || !tail || !head || !cap || !w) return MCF_E_ARG;
-    if (utility != MCF_UTIL_LOG && utility != MCF_UTIL_POWER) return MCF_E_ARG;
+    if (utility != MCF_UTIL_LOG && utility != MCF_UTIL_POWER && utility != MCF_UTIL_ALPHA) return MCF_E_ARG;
     if (utility == MCF_UTIL_POWER && !(gamma > 0.0 && gamma < 1.0)) return MCF_E_ARG;
+    if (utility == MCF_UTIL_ALPHA && !(gamma > 0.0 && gamma <= 16.0 && gamma != 1.0)) return MCF_E_ARG;
     if (!(o.tol > 0.0) || (o.precision != MCF_FP32 && o.precision != MCF_FP64)) return MCF_E_ARG;
     if (o.stop_rule != MCF_STOP_REL_KKT && o.stop_rule != MCF_STOP_PAPER) return MCF_E_ARG;
     if (!(o.rho > 0.0 && o.rho < 2.0) || !(o.omega0 > 0.0) || !(o.theta >= 0.0 && o.theta <= 1.0)) return MCF_E_ARG;
@@ -570,8 +571,9 @@ int mcf_create(int32_t n, int32_t m, const int32_t *tail, const int32_t *head, c
     c.m = m;
     c.ld = s->ld;
     c.utility = utility;
-    c.gamma = utility == MCF_UTIL_POWER ? gamma : 0.0;
-    c.c1 = utility == MCF_UTIL_POWER ? gamma / (1.0 - gamma) : 0.0;
+    c.gamma = utility == MCF_UTIL_LOG ? 0.0 : gamma;
+    // power: c1 = gamma / (1 - gamma) of Section 2.3; alpha-fair: the exponent p = 1 / alpha
+    c.c1 = utility == MCF_UTIL_POWER ? gamma / (1.0 - gamma) : utility == MCF_UTIL_ALPHA ? 1.0 / gamma : 0.0;
     c.rho = o.rho;
     c.theta = o.theta;
     c.tau = o.tau;

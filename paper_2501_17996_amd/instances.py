@@ -23,6 +23,7 @@ import numpy as np
 
 UTIL_LOG = 0
 UTIL_POWER = 1
+UTIL_ALPHA = 2   # alpha-fair: u(s) = w s^(1-alpha) / (1-alpha), alpha > 0, alpha != 1
 
 
 @dataclass
@@ -31,8 +32,8 @@ class Instance:
     tail: np.ndarray          # int32[m]
     head: np.ndarray          # int32[m]
     cap: np.ndarray           # float64[m]
-    utility: int              # UTIL_LOG or UTIL_POWER
-    gamma: float              # exponent of the power utility (ignored for log)
+    utility: int              # UTIL_LOG, UTIL_POWER or UTIL_ALPHA
+    gamma: float              # gamma of the power utility, alpha of the alpha-fair one (ignored for log)
     w: np.ndarray             # float64[n*n], w[j*n+i]
     name: str = ""
     seed: int = 0
@@ -151,7 +152,7 @@ def ring_instance(n: int, deg: int, seed: int, utility: int = UTIL_LOG, gamma: f
     tail, head = ring_plus_outdegree(n, deg, rng)
     cap = rng.uniform(cap_range[0], cap_range[1], size=tail.shape[0])
     w = _weights(n, w_range[0], w_range[1], rng)
-    g = gamma if utility == UTIL_POWER else 0.0
+    g = gamma if utility in (UTIL_POWER, UTIL_ALPHA) else 0.0
     return Instance(n, tail, head, cap, utility, g, w, name=f"ring{n}-deg{deg}", seed=seed)
 
 
@@ -227,5 +228,5 @@ def hub_instance(n: int, seed: int, utility: int = UTIL_LOG, gamma: float = 0.5)
     head = np.concatenate([ring_h, others, hub]).astype(np.int32)
     cap = rng.uniform(0.5, 2.0, size=tail.shape[0])
     w = _weights(n, 0.5, 1.5, rng)
-    g = gamma if utility == UTIL_POWER else 0.0
+    g = gamma if utility in (UTIL_POWER, UTIL_ALPHA) else 0.0
     return Instance(n, tail, head, cap, utility, g, w, name=f"hub{n}", seed=seed)

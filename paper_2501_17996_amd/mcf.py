@@ -21,7 +21,7 @@ except Exception:  # pragma: no cover - torch is optional for the binding
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmcf.so")
 
-MCF_UTIL_LOG, MCF_UTIL_POWER = 0, 1
+MCF_UTIL_LOG, MCF_UTIL_POWER, MCF_UTIL_ALPHA = 0, 1, 2
 MCF_FP64, MCF_FP32 = 0, 1
 MCF_STOP_REL_KKT, MCF_STOP_PAPER = 0, 1
 MCF_OK, MCF_E_ARG, MCF_E_GRAPH, MCF_E_NOMEM, MCF_E_DEVICE, MCF_E_STATE = 0, -1, -2, -3, -4, -5

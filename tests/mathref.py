@@ -22,15 +22,21 @@ def weights_matrix(inst):
 
 
 def util(inst, s, w):
+    """u(s): w log s, w s^gamma, or the alpha-fair w s^(1-alpha)/(1-alpha) (alpha in inst.gamma)."""
     if inst.utility == 0:
         return w * np.log(s)
-    return w * s ** inst.gamma
+    if inst.utility == 1:
+        return w * s ** inst.gamma
+    a = inst.gamma
+    return w * s ** (1.0 - a) / (1.0 - a)
 
 
 def dutil(inst, s, w):
     if inst.utility == 0:
         return w / s
-    return w * inst.gamma * s ** (inst.gamma - 1.0)
+    if inst.utility == 1:
+        return w * inst.gamma * s ** (inst.gamma - 1.0)
+    return w * s ** (-inst.gamma)
 
 
 def offdiag_mask(n):

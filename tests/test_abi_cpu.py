@@ -87,6 +87,8 @@ def test_validation_errors(mcf):
     w = inst.w.copy(); w[0] = np.nan                          # the diagonal is ignored ...
     _expect(mcf, E, w=w, utility=1, gamma=1.0)                # ... but gamma must be in (0, 1)
     _expect(mcf, E, utility=7)
+    for a in (0.0, -1.0, 1.0, 16.5, np.nan, np.inf):          # alpha-fair: 0 < alpha <= 16, alpha != 1
+        _expect(mcf, E, utility=mcf.MCF_UTIL_ALPHA, gamma=a)
     _expect(mcf, E, n=1)
     o = mcf.mcf_options_default(); o.tol = 0.0
     _expect(mcf, E, opt=o)

@@ -138,6 +138,31 @@ def test_pool_agrees_with_single_instance_solver(M):
         assert pst["primal_obj"] == pytest.approx(st["primal_obj"], rel=1e-9)
 
 
+def test_pool_alpha_fair_alone_equals_mix_and_single(M):
+    """An alpha-fair instance (alpha = 2) in the pool: bitwise the same alone and beside log and
+    power instances, and the single-instance solver's objective (FP64, 1e-9)."""
+    a = I.ring_instance(90, 5, seed=77, utility=I.UTIL_ALPHA, gamma=2.0)
+    insts = [a] + _mix()[:3]
+    tol = 1e-4
+    pool = M.Pool(0, max_slots=1, check_every=K)
+    h = _solver(M, a, 0, tol)
+    sl = pool.admit(h)
+    alone = _drain(M, pool, [h], [sl])[sl]
+    pool.close()
+    pool = M.Pool(0, max_slots=len(insts), check_every=K)
+    hs = [_solver(M, inst, 0, tol) for inst in insts]
+    sls = [pool.admit(h) for h in hs]
+    mix = _drain(M, pool, hs, sls)[sls[0]]
+    assert alone[0]["state_name"] == mix[0]["state_name"] == "converged"
+    assert alone[0]["iters"] == mix[0]["iters"]
+    for x, y in zip(alone[1:], mix[1:]):
+        np.testing.assert_array_equal(x, y)
+    st = _solver(M, a, 0, tol).solve()
+    assert abs(st["iters"] - alone[0]["iters"]) <= K
+    assert alone[0]["primal_obj"] == pytest.approx(st["primal_obj"], rel=1e-9)
+    print(f"alpha-fair in the pool: iters {alone[0]['iters']} single {st['iters']}", flush=True)
+
+
 def test_pool_fp32_objective_matches_fp64(M):
     insts = _mix()
     out = {}

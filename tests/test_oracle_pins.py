@@ -103,7 +103,12 @@ def _prox_conj_by_moreau(y, beta, w, inst_util, gamma):
     v = y / beta
 
     def obj(s):
-        u = w * math.log(s) if inst_util == 0 else w * s ** gamma
+        if inst_util == 0:
+            u = w * math.log(s)
+        elif inst_util == 1:
+            u = w * s ** gamma
+        else:
+            u = w * s ** (1.0 - gamma) / (1.0 - gamma)
         return -u / beta + 0.5 * (s - v) ** 2
 
     hi = 4.0 * (abs(v) + math.sqrt(w / beta) + w / beta) + 10.0   # above the minimizer
@@ -143,6 +148,53 @@ def test_prox_power_general_gamma(orc, gamma, y):
     z = orc.prox_power(y, beta, w, gamma)
     assert z < 0
     assert z == pytest.approx(_prox_conj_by_moreau(y, beta, w, 1, gamma), rel=1e-6, abs=1e-8 * max(1.0, abs(y)))
+
+
+# alpha-fair utility u(s) = w s^(1-a)/(1-a): the general strictly concave increasing u of
+# Section 1.1, whose scalar prox Section 2.3 leaves to the general case
+@pytest.mark.parametrize("y", [-5.0, -1.0, -0.01, 0.0, 0.3, 2.0, 40.0])
+@pytest.mark.parametrize("beta,w", [(0.2, 1.0), (3.0, 0.6), (0.01, 1.4)])
+def test_prox_alpha_two_cardano(orc, y, beta, w):
+    """a = 2 (u = -w/s, traffic s(z) = sqrt(w/-z)): with r = sqrt(-z) the optimality condition
+    z + beta s(z) = y is the depressed cubic r^3 + y r - beta sqrt(w) = 0, solved by Cardano's
+    formula (one real root when the discriminant is positive, else the largest of three)."""
+    z = orc.prox_alpha(y, beta, w, 2.0)
+    assert z < 0
+    P, Q = y, -beta * math.sqrt(w)
+    disc = (Q / 2) ** 2 + (P / 3) ** 3
+    if disc >= 0:
+        sq = math.sqrt(disc)
+        r = float(np.cbrt(-Q / 2 + sq) + np.cbrt(-Q / 2 - sq))
+    else:
+        r = 2 * math.sqrt(-P / 3) * math.cos(math.acos((3 * Q / (2 * P)) * math.sqrt(-3 / P)) / 3)
+    assert -z == pytest.approx(r * r, rel=1e-9)
+
+
+@pytest.mark.parametrize("alpha", [0.3, 0.5, 0.8])
+@pytest.mark.parametrize("y", [-3.0, -0.1, 0.0, 1.5])
+def test_prox_alpha_below_one_is_power(orc, alpha, y):
+    """For a < 1, w s^(1-a)/(1-a) is the power utility with gamma = 1 - a and weight w/(1-a)."""
+    beta, w = 0.4, 1.2
+    z = orc.prox_alpha(y, beta, w, alpha)
+    assert z == pytest.approx(orc.prox_power(y, beta, w / (1 - alpha), 1 - alpha), rel=1e-12)
+
+
+@pytest.mark.parametrize("y", [-3.0, -0.1, 0.0, 1.5, 30.0])
+def test_prox_alpha_near_one_is_log(orc, y):
+    """w s^(1-a)/(1-a) = w/(1-a) + w log s + O(1-a); the constant does not move the prox."""
+    for a in (1 - 1e-7, 1 + 1e-7):
+        assert orc.prox_alpha(y, 0.4, 1.2, a) == pytest.approx(orc.prox_log(y, 0.4, 1.2), rel=1e-5)
+
+
+@pytest.mark.parametrize("alpha", [1.5, 2.5, 4.0, 8.0, 16.0])
+@pytest.mark.parametrize("y", [-4.0, -0.2, 0.0, 0.7, 25.0])
+def test_prox_alpha_general(orc, alpha, y):
+    beta, w = 0.3, 0.9
+    z = orc.prox_alpha(y, beta, w, alpha)
+    assert z < 0
+    # optimality: z + beta s(z) = y, s(z) = (w/-z)^(1/a) the traffic that price z asks for
+    assert z + beta * (w / -z) ** (1 / alpha) == pytest.approx(y, abs=1e-12 * max(1.0, abs(y)))
+    assert z == pytest.approx(_prox_conj_by_moreau(y, beta, w, 2, alpha), rel=1e-6, abs=1e-8 * max(1.0, abs(y)))
 
 
 # ----------------------------------------------------------------------- eta
