@@ -28,15 +28,22 @@ HBM_PEAK_GBS = 8000.0
 def measured_traffic(workload: str):
     """HBM bytes per launch of the dominant kernel from the committed counter runs, or None
     when the kernel source changed after the counters were taken."""
-    import hashlib
     try:
         rec = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))
-        src = open(os.path.join(ROOT, "paper_2501_17996_amd", "csrc", "mcf_kernels.hip"), "rb").read()
     except OSError:
         return None
-    if hashlib.sha256(src).hexdigest() != rec.get("kernels_sha256") or workload not in rec:
+    if kernels_sha256() != rec.get("kernels_sha256") or workload not in rec:
         return None
     return rec[workload]["bytes_per_launch"]
+
+
+def kernels_sha256() -> str:
+    """Hash of the kernel source and the launch-shape table the traffic figures belong to."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("mcf_kernels.hip", "tuned_shapes.inc"):
+        h.update(open(os.path.join(ROOT, "paper_2501_17996_amd", "csrc", f), "rb").read())
+    return h.hexdigest()
 
 
 def workload(name: str):

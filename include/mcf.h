@@ -72,6 +72,15 @@ typedef struct {
     size_t workspace_bytes;
     int64_t adapt_until;    /* omega is adapted only while k < adapt_until (-1: always).  Section 2.4 notes that
                                freezing omega after some iterations restores the constant-omega convergence proof */
+    /* Launch shape of the two-phase iteration; 0 = the measured choice for this n and precision
+     * (the table tune.py writes).  edge_waves: 1 = one wave per out-edge, eight out-edges of a
+     * tail at once; 4, 8 or 16 = that many waves per edge column, the out-edges of a tail in turn.
+     * edge_vectors: 16-byte vectors per lane of a column.  The pair must be one that
+     * mcf_edge_shapes lists and whose columns hold n entries (64 * waves * vectors * 16 / size
+     * of the iterate), else MCF_E_ARG; both or neither are given.  node_block: 64 or 256
+     * threads per node-phase block.  Results depend on the shape only through the order of
+     * floating-point sums. */
+    int32_t edge_waves, edge_vectors, node_block;
 } mcf_options;
 
 /* Latest solve record.  Residuals are those of the last checked iteration:
@@ -163,6 +172,11 @@ int mcf_debug_poison(mcf_solver *s, int32_t which, int64_t index);
  * summed milliseconds and the number of bracketed iterations since the last enable. */
 int mcf_enable_kernel_timing(mcf_solver *s, int32_t enable);
 int mcf_kernel_time(mcf_solver *s, double *edge_ms, int64_t *edge_launches);
+
+/* The two-phase edge shapes compiled into the library for this precision: writes up to cap
+ * (waves, vectors) pairs (waves 1 = the concurrent form) and returns how many there are
+ * (0 for an invalid precision). */
+int32_t mcf_edge_shapes(int32_t precision, int32_t *waves, int32_t *vectors, int32_t cap);
 
 /* Internal sizes chosen at create: padded leading dimension, threads per edge column,
  * entries per thread, and the kernel organisation in use (MCF_KERNELS_TWO_PHASE or _FUSED). */

@@ -6,7 +6,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libmcf.so")
 SOURCES = [os.path.join(HERE, "csrc", f) for f in ("mcf_kernels.hip", "mcf_runtime.hip")]
-HEADERS = [os.path.join(HERE, "csrc", "mcf_internal.h"), os.path.join(ROOT, "include", "mcf.h")]
+HEADERS = [os.path.join(HERE, "csrc", "mcf_internal.h"), os.path.join(HERE, "csrc", "tuned_shapes.inc"),
+           os.path.join(ROOT, "include", "mcf.h")]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",

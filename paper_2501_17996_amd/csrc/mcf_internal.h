@@ -93,6 +93,10 @@ struct EdgeShape {
 // Waves per workgroup of the concurrent edge phase.
 constexpr int EDGE_PAR_WAVES = 8;
 EdgeShape edge_shape_for(int n, int bytes);
+// the compiled two-phase edge shapes for iterate size `bytes`; whether `sh` is one of them and
+// its columns hold n entries
+int edge_shape_list(int bytes, const EdgeShape **list);
+bool edge_shape_valid(EdgeShape sh, int n, int bytes);
 
 // Kernel launchers (defined in mcf_kernels.hip).
 template <typename T>
@@ -122,7 +126,7 @@ hipError_t launch_poison(const Bufs<T> &b, int which, long long offset, hipStrea
 template <typename T>
 hipError_t launch_p_from_f(const Consts &c, const Bufs<T> &b, hipStream_t st);
 
-int node_block_for(int n);
+int node_block_for(int n, int bytes);
 
 // One slot of a batching pool: the instance and the values recorded when it was admitted.
 // At pool iteration G the slot performs its iteration k = k0 + (G - G0), reading buffer set

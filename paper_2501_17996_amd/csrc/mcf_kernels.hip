@@ -1517,7 +1517,54 @@ __global__ void pool_gather_kernel(const SlotDesc<T> *slots, int nslots, DevScal
 // that the tail's waves share each column: each lane holds 2 * NV * VEC iterate values (F and
 // q), with the out-edge sums in LDS; eight waves per tail node from n = 4096 on (FP32) keep that
 // near 100 VGPRs, sixteen for FP64 beyond n = 8192.
-EdgeShape edge_shape_for(int n, int bytes)
+// Two-phase edge launch shapes compiled below, per iterate size.  {1, nv, 1}: edge_kernel_par
+// (one wave per out-edge, columns of up to 64 nv vec entries); {wpe, nv, 0}: edge_kernel with
+// wpe waves per column of up to 64 wpe nv vec entries, the out-edges of a tail in turn.
+static const EdgeShape EDGE_SHAPES_F32[] = {{1, 1, 1}, {1, 2, 1}, {1, 4, 1}, {1, 8, 1}, {4, 1, 0}, {4, 2, 0},
+                                            {4, 4, 0}, {8, 3, 0}, {8, 4, 0}, {8, 6, 0}, {8, 8, 0}};
+static const EdgeShape EDGE_SHAPES_F64[] = {{1, 1, 1}, {1, 2, 1}, {1, 4, 1}, {1, 8, 1}, {4, 1, 0},
+                                            {4, 2, 0}, {4, 4, 0}, {8, 4, 0}, {8, 8, 0}, {16, 8, 0}};
+
+int edge_shape_list(int bytes, const EdgeShape **list)
+{
+    if (bytes == 4) {
+        *list = EDGE_SHAPES_F32;
+        return (int)(sizeof(EDGE_SHAPES_F32) / sizeof(EdgeShape));
+    }
+    *list = EDGE_SHAPES_F64;
+    return (int)(sizeof(EDGE_SHAPES_F64) / sizeof(EdgeShape));
+}
+
+bool edge_shape_valid(EdgeShape sh, int n, int bytes)
+{
+    const EdgeShape *list;
+    const int cnt = edge_shape_list(bytes, &list);
+    for (int x = 0; x < cnt; ++x)
+        if (list[x].wpe == sh.wpe && list[x].ept == sh.ept && list[x].par == sh.par)
+            return n <= 64 * sh.wpe * (16 / bytes) * sh.ept;
+    return false;
+}
+
+// Shapes picked by measurement: the table is written by paper_2501_17996_amd/tune.py, which
+// times every compiled shape and node block on the GPU at a ladder of sizes.  Entries are
+// ascending in n_max per iterate size; an entry applies to every n up to its n_max above the
+// previous one's.  The choice depends on (n, iterate size) only, so results stay deterministic.
+struct TunedEntry {
+    int bytes, n_max;
+    EdgeShape sh;
+    int node_block;
+};
+#include "tuned_shapes.inc"
+
+static const TunedEntry *tuned_for(int n, int bytes)
+{
+    for (const TunedEntry &t : TUNED_SHAPES)
+        if (t.bytes == bytes && n <= t.n_max) return &t;
+    return nullptr;
+}
+
+// Without a table entry: the smallest shape whose columns cover n.
+static EdgeShape edge_shape_default(int n, int bytes)
 {
     const int vec = 16 / bytes;
     const int nvp[] = {1, 2, 4, 8};
@@ -1537,7 +1584,19 @@ EdgeShape edge_shape_for(int n, int bytes)
     return {16, 8, 0};
 }
 
-int node_block_for(int n) { return n <= 512 ? 64 : 256; }
+EdgeShape edge_shape_for(int n, int bytes)
+{
+    const TunedEntry *t = tuned_for(n, bytes);
+    if (t && edge_shape_valid(t->sh, n, bytes)) return t->sh;
+    return edge_shape_default(n, bytes);
+}
+
+int node_block_for(int n, int bytes)
+{
+    const TunedEntry *t = tuned_for(n, bytes);
+    if (t && (t->node_block == 64 || t->node_block == 256)) return t->node_block;
+    return n <= 512 ? 64 : 256;
+}
 
 template <typename T>
 hipError_t launch_init(const Consts &c, const Bufs<T> &b, double omega0, hipStream_t st)

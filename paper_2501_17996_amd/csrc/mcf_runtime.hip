@@ -25,9 +25,8 @@ size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
 long long padded_ld(int n) { return (long long)((n + 63) / 64) * 64; }
 
-int node_blocks(int n)
+int node_blocks(int n, int nb)
 {
-    const int nb = node_block_for(n);
     return ((n + nb - 1) / nb) * n;
 }
 
@@ -59,12 +58,12 @@ struct Plan {
 
 bool use_fused(int n, int mode) { return mode == MCF_KERNELS_FUSED || (mode == MCF_KERNELS_AUTO && n <= FUSED_MAX_N); }
 
-Plan make_plan(int n, int m, int precision, bool fused)
+Plan make_plan(int n, int m, int precision, bool fused, int node_block)
 {
     const size_t es = precision == MCF_FP32 ? 4 : 8;
     const size_t ld = (size_t)padded_ld(n);
     const size_t nm = ld * (size_t)m, nn = ld * (size_t)n;
-    const PartLayout pl = part_layout(m, node_blocks(n));
+    const PartLayout pl = part_layout(m, node_blocks(n, node_block));
     Plan p;
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes); return at; };
@@ -495,7 +494,20 @@ void mcf_options_default(mcf_options *o)
 size_t mcf_workspace_bytes(int32_t n, int32_t m, int32_t precision)
 {
     if (n < 2 || n > MAX_N || m < 1 || (precision != MCF_FP32 && precision != MCF_FP64)) return 0;
-    return make_plan(n, m, precision, use_fused(n, MCF_KERNELS_AUTO)).total;
+    return make_plan(n, m, precision, use_fused(n, MCF_KERNELS_AUTO),
+                     node_block_for(n, precision == MCF_FP32 ? 4 : 8)).total;
+}
+
+int32_t mcf_edge_shapes(int32_t precision, int32_t *waves, int32_t *vectors, int32_t cap)
+{
+    if (precision != MCF_FP32 && precision != MCF_FP64) return 0;
+    const EdgeShape *list;
+    const int cnt = edge_shape_list(precision == MCF_FP32 ? 4 : 8, &list);
+    for (int x = 0; x < cnt && x < cap; ++x) {
+        if (waves) waves[x] = list[x].par ? 1 : list[x].wpe;
+        if (vectors) vectors[x] = list[x].ept;
+    }
+    return cnt;
 }
 
 const char *mcf_strerror(int code)
@@ -543,6 +555,18 @@ int mcf_create(int32_t n, int32_t m, const int32_t *tail, const int32_t *head, c
     if (o.check_every < 1) o.check_every = 1;
     if (o.kernel_mode < MCF_KERNELS_AUTO || o.kernel_mode > MCF_KERNELS_FUSED) return MCF_E_ARG;
     if (o.kernel_mode == MCF_KERNELS_FUSED && n > FUSED_MAX_N) return MCF_E_ARG;
+    const int bytes = o.precision == MCF_FP32 ? 4 : 8;
+    EdgeShape shape = edge_shape_for(n, bytes);
+    if (o.edge_waves != 0 || o.edge_vectors != 0) {
+        const EdgeShape want{o.edge_waves, o.edge_vectors, o.edge_waves == 1 ? 1 : 0};
+        if (!edge_shape_valid(want, n, bytes)) return MCF_E_ARG;
+        shape = want;
+    }
+    int node_block = node_block_for(n, bytes);
+    if (o.node_block != 0) {
+        if (o.node_block != 64 && o.node_block != 256) return MCF_E_ARG;
+        node_block = o.node_block;
+    }
     for (int l = 0; l < m; ++l) {
         if (tail[l] < 0 || tail[l] >= n || head[l] < 0 || head[l] >= n || tail[l] == head[l]) return MCF_E_ARG;
         if (!(cap[l] > 0.0) || !std::isfinite(cap[l])) return MCF_E_ARG;
@@ -562,10 +586,10 @@ int mcf_create(int32_t n, int32_t m, const int32_t *tail, const int32_t *head, c
     s->precision = o.precision;
     s->opt = o;
     s->ld = padded_ld(n);
-    s->sh = edge_shape_for(n, o.precision == MCF_FP32 ? 4 : 8);
+    s->sh = shape;
     const bool fused = use_fused(n, o.kernel_mode);
-    s->plan = make_plan(n, m, o.precision, fused);
-    s->pl = part_layout(m, node_blocks(n));
+    s->plan = make_plan(n, m, o.precision, fused, node_block);
+    s->pl = part_layout(m, node_blocks(n, node_block));
     Consts &c = s->c;
     c.n = n;
     c.m = m;
@@ -581,8 +605,8 @@ int mcf_create(int32_t n, int32_t m, const int32_t *tail, const int32_t *head, c
     c.k_adapt = o.k_adapt;
     c.adapt_until = o.adapt_until;
     c.stop_rule = o.stop_rule;
-    c.nblk_node = node_blocks(n);
-    c.node_block = node_block_for(n);
+    c.nblk_node = node_blocks(n, node_block);
+    c.node_block = node_block;
     c.fused = fused ? 1 : 0;
     c.edge_par = s->sh.par;
     c.nep = n;  // edge quantities are added per tail node

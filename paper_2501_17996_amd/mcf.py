@@ -32,7 +32,7 @@ STATE_NAMES = {0: "running", 1: "converged", 2: "max_iter", 3: "diverged"}
 EXPORTED = [
     "mcf_options_default", "mcf_workspace_bytes", "mcf_create", "mcf_solve", "mcf_run", "mcf_reset",
     "mcf_status", "mcf_get_solution", "mcf_get_state", "mcf_set_state", "mcf_destroy", "mcf_strerror",
-    "mcf_debug_poison", "mcf_enable_kernel_timing", "mcf_kernel_time", "mcf_layout",
+    "mcf_debug_poison", "mcf_enable_kernel_timing", "mcf_kernel_time", "mcf_layout", "mcf_edge_shapes",
     "mcf_pool_create", "mcf_pool_admit", "mcf_pool_step", "mcf_pool_sync", "mcf_pool_poll", "mcf_pool_retire",
     "mcf_pool_info", "mcf_pool_destroy",
 ]
@@ -45,7 +45,8 @@ class mcf_options(ctypes.Structure):
                 ("rho", ctypes.c_double), ("theta", ctypes.c_double), ("tau", ctypes.c_double),
                 ("omega0", ctypes.c_double), ("device", ctypes.c_int32), ("kernel_mode", ctypes.c_int32),
                 ("stream", ctypes.c_void_p), ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t),
-                ("adapt_until", ctypes.c_int64)]
+                ("adapt_until", ctypes.c_int64), ("edge_waves", ctypes.c_int32), ("edge_vectors", ctypes.c_int32),
+                ("node_block", ctypes.c_int32)]
 
 
 class mcf_result(ctypes.Structure):
@@ -102,6 +103,8 @@ def lib():
         L.mcf_enable_kernel_timing.argtypes = [_vp, ctypes.c_int32]
         L.mcf_kernel_time.argtypes = [_vp, _dp, ctypes.POINTER(ctypes.c_int64)]
         L.mcf_layout.argtypes = [_vp, _ip, _ip, _ip, _ip]
+        L.mcf_edge_shapes.argtypes = [ctypes.c_int32, _ip, _ip, ctypes.c_int32]
+        L.mcf_edge_shapes.restype = ctypes.c_int32
         L.mcf_pool_create.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_size_t, ctypes.c_int32, ctypes.c_int32,
                                       _vp, ctypes.POINTER(_vp)]
         L.mcf_pool_admit.argtypes = [_vp, _vp, _ip]
@@ -220,6 +223,15 @@ def mcf_layout(h):
     _check(lib().mcf_layout(h, ctypes.byref(ld), ctypes.byref(b), ctypes.byref(e), ctypes.byref(km)), "mcf_layout")
     return {"ld": ld.value, "edge_block": b.value, "edge_ept": e.value,
             "kernel_mode": {1: "two_phase", 2: "fused"}.get(km.value, "?")}
+
+
+def mcf_edge_shapes(precision: int):
+    """The compiled two-phase edge shapes as (edge_waves, edge_vectors) pairs."""
+    cnt = lib().mcf_edge_shapes(int(precision), None, None, 0)
+    wv = (ctypes.c_int32 * max(cnt, 1))()
+    vc = (ctypes.c_int32 * max(cnt, 1))()
+    lib().mcf_edge_shapes(int(precision), wv, vc, cnt)
+    return [(int(wv[x]), int(vc[x])) for x in range(cnt)]
 
 
 # --------------------------------------------------------------- convenience

@@ -96,6 +96,48 @@ def test_validation_errors(mcf):
     _expect(mcf, E, opt=o)
 
 
+def test_forced_launch_shapes_are_validated(mcf):
+    """A forced two-phase shape must be compiled and hold the columns; a node block is 64 or 256."""
+    E = mcf.MCF_E_ARG
+
+    def opt(**kw):
+        o = mcf.mcf_options_default()
+        for k, v in kw.items():
+            setattr(o, k, v)
+        return o
+    _expect(mcf, E, opt=opt(edge_waves=3, edge_vectors=1))      # not a compiled shape
+    _expect(mcf, E, opt=opt(edge_waves=4))                      # the pair is given together
+    _expect(mcf, E, opt=opt(edge_vectors=2))
+    _expect(mcf, E, opt=opt(node_block=128))
+    _expect(mcf, E, opt=opt(precision=0, edge_waves=8, edge_vectors=3))   # compiled for FP32 only ...
+    big = I.ring_instance(3000, 2, seed=1)                       # ... and columns of 64*1*2*2 < 3000
+    with pytest.raises(mcf.MCFError) as ei:
+        mcf.mcf_create(big.n, big.tail, big.head, big.cap, big.utility, big.gamma, big.w,
+                       opt(edge_waves=1, edge_vectors=2))
+    assert ei.value.code == E
+    assert (8, 3) in mcf.mcf_edge_shapes(1) and (8, 3) not in mcf.mcf_edge_shapes(0)
+    assert mcf.mcf_edge_shapes(7) == []
+
+
+def test_tuned_table_is_well_formed(mcf):
+    """Every entry of the measured table names a compiled shape that holds its n_max, with
+    n_max ascending per iterate size."""
+    import re
+    path = os.path.join(os.path.dirname(mcf.LIB_PATH), "csrc", "tuned_shapes.inc")
+    ent = re.findall(r"\{(\d+), (\d+), \{(\d+), (\d+), (\d+)\}, (\d+)\}", open(path).read())
+    last = {}
+    for b, n_max, waves, vectors, par, nb in (tuple(map(int, e)) for e in ent):
+        if b == 0:
+            continue   # sentinel
+        precision = 1 if b == 4 else 0
+        assert b in (4, 8) and nb in (64, 256)
+        assert par == (1 if waves == 1 else 0)
+        assert (waves, vectors) in mcf.mcf_edge_shapes(precision)
+        assert n_max <= 64 * waves * vectors * (16 // b)
+        assert n_max > last.get(b, 0)
+        last[b] = n_max
+
+
 def test_graph_not_strongly_connected(mcf):
     # a directed path 0 -> 1 -> 2 plus 2 -> 1: node 0 is never reached back
     tail = np.array([0, 1, 2], np.int32)

@@ -305,6 +305,28 @@ def test_hub_node_trajectory(M, mode):
     _checkpoints(M, inst, mode, (1, 2, 30, 100))
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_every_compiled_shape_matches_oracle(M, precision):
+    """Every two-phase edge shape the library can launch, with both node blocks, on one instance
+    whose columns all of them hold: FP64 to 1e-10 of the oracle, FP32 to FP32 rounding."""
+    inst = I.ring_instance(100, 6, seed=11)
+    O = oracle.OracleSolver(inst, threads=THREADS)
+    O.run(3, check=False)
+    Fo, Yo, _ = O.get_state()
+    tol = RTOL64 if precision == 0 else 1e-5
+    shapes = M.mcf_edge_shapes(precision)
+    assert len(shapes) >= 10
+    for waves, vectors in shapes:
+        for nb in (64, 256):
+            S = gpu_solver(M, inst, precision=precision, kernel_mode=M.MCF_KERNELS_TWO_PHASE,
+                           edge_waves=waves, edge_vectors=vectors, node_block=nb)
+            S.run(3)
+            Fg, Yg, _ = S.get_state()
+            ef, ey = relerr(Fg, Fo), relerr(Yg, Yo)
+            assert ef <= tol and ey <= tol, (waves, vectors, nb, ef, ey)
+            S.close()
+
+
 def test_c3_fp64_first_iterations(M):
     inst = I.config3(0)
     S = gpu_solver(M, inst)
