@@ -942,11 +942,11 @@ __global__ __launch_bounds__(NB) void p_from_f_kernel(Consts c, Bufs<T> b)
 
 // ----------------------------------------------------- fused node iteration
 // For n <= 64*EPT <= FUSED_MAX_N one PDHG iteration is a single launch: workgroup j
-// (four waves) recomputes, one wave per column, the projection of every edge incident
-// to node j (an edge is projected by both of its end nodes, from identical inputs with
-// identical code, so both get the same bits), accumulates V[:,j] = sum_in Fbar - sum_out
-// Fbar in registers, adds the four waves' sums in wave order through LDS, and updates
-// Y[:,j].  The tail's workgroup writes the edge's new F column and multiplier.  F, Y and
+// (fused_waves: 16 waves on regular iterations with up to 4 entries per lane, else 8)
+// recomputes, one wave per column, the projection of every edge incident to node j (an edge
+// is projected by both of its end nodes, from identical inputs with identical code, so both
+// get the same bits), accumulates V[:,j] = sum_in Fbar - sum_out Fbar in registers, adds the
+// waves' sums in wave order through LDS, and updates Y[:,j].  The tail's workgroup writes the edge's new F column and multiplier.  F, Y and
 // mu are read from one buffer set and written to the other, so no workgroup can see a
 // value of the iteration in flight.
 template <int EPT, bool CHECK>
@@ -1508,16 +1508,11 @@ __global__ void pool_gather_kernel(const SlotDesc<T> *slots, int nslots, DevScal
 }
 
 // ---------------------------------------------------------------- launchers
-// Waves per edge column and 16-byte vectors per lane for an n-row column of an iterate of
-// `bytes`-byte entries: enough lanes to cover n, with a 256-thread block (four waves) for
-// large n so that several blocks stay resident on a CU, and 512 threads for the largest
-// FP64 columns to keep the per-lane register count bounded.
-// Edge phase shapes.  Up to n = 64 * 8 * VEC (2048 FP32, 1024 FP64) a column fits one wave with
-// at most 8 vectors per lane, and the tail's out-edges are projected concurrently (par).  Beyond
-// that the tail's waves share each column: each lane holds 2 * NV * VEC iterate values (F and
-// q), with the out-edge sums in LDS; eight waves per tail node from n = 4096 on (FP32) keep that
-// near 100 VGPRs, sixteen for FP64 beyond n = 8192.
-// Two-phase edge launch shapes compiled below, per iterate size.  {1, nv, 1}: edge_kernel_par
+// Two-phase edge launch shapes compiled below, per iterate size.  Up to n = 64 * 8 * VEC (2048
+// FP32, 1024 FP64) a column fits one wave with at most 8 vectors per lane, and a tail's
+// out-edges can be projected concurrently.  Beyond that a tail's waves share each column: each
+// lane holds 2 * NV * VEC iterate values (F and q), with the out-edge sums in LDS; 8 waves per
+// column keep that near 100 VGPRs, 16 for the largest FP64 columns.  {1, nv, 1}: edge_kernel_par
 // (one wave per out-edge, columns of up to 64 nv vec entries); {wpe, nv, 0}: edge_kernel with
 // wpe waves per column of up to 64 wpe nv vec entries, the out-edges of a tail in turn.
 static const EdgeShape EDGE_SHAPES_F32[] = {{1, 1, 1}, {1, 2, 1}, {1, 4, 1}, {1, 8, 1}, {4, 1, 0}, {4, 2, 0},
