@@ -81,6 +81,11 @@ typedef struct {
      * threads per node-phase block.  Results depend on the shape only through the order of
      * floating-point sums. */
     int32_t edge_waves, edge_vectors, node_block;
+    /* 1 (default): each block of check_every iterations is captured once per block shape into a
+     * HIP graph and replayed, which shortens the gap between dependent launches; 0: launched one
+     * by one.  Results are the same either way.  Kernel timing (mcf_enable_kernel_timing) always
+     * launches directly. */
+    int32_t graphs;
 } mcf_options;
 
 /* Latest solve record.  Residuals are those of the last checked iteration:
@@ -108,7 +113,7 @@ typedef struct {
 
 /* Fills *o with the defaults: tol 1e-4, REL_KKT, FP64, check_every 1, max_iter 100000,
  * k_adapt 100, rho 1.9, theta 0.5, tau 1e-5, omega0 1, adapt_until -1, device 0, no stream,
- * no workspace. */
+ * no workspace, measured launch shapes, graphs 1. */
 void mcf_options_default(mcf_options *o);
 
 /* Device bytes one instance needs at this precision with the kernel organisation AUTO picks

@@ -116,10 +116,11 @@ hipError_t launch_fused(const Consts &c, const Bufs<T> &b, const PartLayout &pl,
 template <typename T>
 hipError_t launch_residual(const Consts &c, const Bufs<T> &b, const PartLayout &pl, EdgeShape sh,
                            hipStream_t st);
-// `adapt`: apply (e-primal_weight) if the step norms exceed tau; `k_after`: iterations done after this one.
+// `adapt`: apply (e-primal_weight) if the step norms exceed tau; `k_inc`: iterations since the
+// previous control launch (the device count advances by it).
 template <typename T>
 hipError_t launch_control(const Consts &c, const Bufs<T> &b, const PartLayout &pl, bool check, bool adapt,
-                          long long k_after, hipStream_t st);
+                          long long k_inc, hipStream_t st);
 template <typename T>
 hipError_t launch_poison(const Bufs<T> &b, int which, long long offset, hipStream_t st);
 // Two-phase iteration: P = F A^T recomputed from the current F (after F is set from outside).

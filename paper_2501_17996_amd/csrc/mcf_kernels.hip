@@ -1403,12 +1403,16 @@ __device__ __forceinline__ void control_body(const Consts &c, const Bufs<T> &b, 
     }
 }
 
+// k_inc: iterations since the previous control launch, so that a captured block of iterations
+// carries no absolute iteration number (the count is read before control_body's barriers, and
+// only thread 0 writes it back after them).
 template <typename T>
 __global__ __launch_bounds__(CTRL_BLOCK) void control_kernel(Consts c, Bufs<T> b, PartLayout pl, int check,
-                                                              int adapt, long long k_after)
+                                                              int adapt, long long k_inc)
 {
     __shared__ double lds[NQ * (CTRL_BLOCK / 64)];
     if (b.sc->stop) return;
+    const long long k_after = b.sc->k + k_inc;
     control_body<T>(c, b, pl, check, adapt, k_after, lds);
 }
 
@@ -1508,6 +1512,14 @@ __global__ void pool_gather_kernel(const SlotDesc<T> *slots, int nslots, DevScal
 }
 
 // ---------------------------------------------------------------- launchers
+// A launch that records the timing events e0/e1 with its own dispatch when they are given, else
+// a plain launch (the form a captured graph takes).
+#define MCF_LAUNCH(kern, grid, block, lds, st, e0, e1, flags, ...)                                \
+    do {                                                                                       \
+        if ((e0) || (e1)) hipExtLaunchKernelGGL(kern, grid, block, lds, st, e0, e1, flags, __VA_ARGS__); \
+        else hipLaunchKernelGGL(kern, grid, block, lds, st, __VA_ARGS__);                       \
+    } while (0)
+
 // Two-phase edge launch shapes compiled below, per iterate size.  Up to n = 64 * 8 * VEC (2048
 // FP32, 1024 FP64) a column fits one wave with at most 8 vectors per lane, and a tail's
 // out-edges can be projected concurrently.  Beyond that a tail's waves share each column: each
@@ -1606,11 +1618,11 @@ static void edge_go(const Consts &c, const Bufs<T> &b, const PartLayout &pl, boo
 {
     const dim3 grid(xcd_grid(WPE == 1 ? (c.n + 3) / 4 : c.n)), block(WPE == 1 ? 256 : 64 * WPE);
     if (check)
-        hipExtLaunchKernelGGL((edge_kernel<T, WPE, NV, true, true>), grid, block, 0, st, e0, e1, 0, c, b, pl);
+        MCF_LAUNCH((edge_kernel<T, WPE, NV, true, true>), grid, block, 0, st, e0, e1, 0, c, b, pl);
     else if (partial)
-        hipExtLaunchKernelGGL((edge_kernel<T, WPE, NV, false, true>), grid, block, 0, st, e0, e1, 0, c, b, pl);
+        MCF_LAUNCH((edge_kernel<T, WPE, NV, false, true>), grid, block, 0, st, e0, e1, 0, c, b, pl);
     else
-        hipExtLaunchKernelGGL((edge_kernel<T, WPE, NV, false, false>), grid, block, 0, st, e0, e1, 0, c, b, pl);
+        MCF_LAUNCH((edge_kernel<T, WPE, NV, false, false>), grid, block, 0, st, e0, e1, 0, c, b, pl);
 }
 
 template <typename T, int NV>
@@ -1619,11 +1631,11 @@ static void edge_par_go(const Consts &c, const Bufs<T> &b, const PartLayout &pl,
 {
     const dim3 grid(xcd_grid(c.n)), block(64 * EDGE_PAR_WAVES);
     if (check)
-        hipExtLaunchKernelGGL((edge_kernel_par<T, NV, true, true>), grid, block, 0, st, e0, e1, 0, c, b, pl);
+        MCF_LAUNCH((edge_kernel_par<T, NV, true, true>), grid, block, 0, st, e0, e1, 0, c, b, pl);
     else if (partial)
-        hipExtLaunchKernelGGL((edge_kernel_par<T, NV, false, true>), grid, block, 0, st, e0, e1, 0, c, b, pl);
+        MCF_LAUNCH((edge_kernel_par<T, NV, false, true>), grid, block, 0, st, e0, e1, 0, c, b, pl);
     else
-        hipExtLaunchKernelGGL((edge_kernel_par<T, NV, false, false>), grid, block, 0, st, e0, e1, 0, c, b, pl);
+        MCF_LAUNCH((edge_kernel_par<T, NV, false, false>), grid, block, 0, st, e0, e1, 0, c, b, pl);
 }
 
 template <typename T>
@@ -1661,9 +1673,9 @@ static void node_go(const Consts &c, const Bufs<T> &b, const PartLayout &pl, boo
                     hipEvent_t e0, hipEvent_t e1)
 {
     const dim3 grid((c.n + NB - 1) / NB, c.n);
-    if (check) hipExtLaunchKernelGGL((node_kernel<T, NB, UTIL, true, true>), grid, dim3(NB), 0, st, e0, e1, 0, c, b, pl);
-    else if (partial) hipExtLaunchKernelGGL((node_kernel<T, NB, UTIL, false, true>), grid, dim3(NB), 0, st, e0, e1, 0, c, b, pl);
-    else hipExtLaunchKernelGGL((node_kernel<T, NB, UTIL, false, false>), grid, dim3(NB), 0, st, e0, e1, 0, c, b, pl);
+    if (check) MCF_LAUNCH((node_kernel<T, NB, UTIL, true, true>), grid, dim3(NB), 0, st, e0, e1, 0, c, b, pl);
+    else if (partial) MCF_LAUNCH((node_kernel<T, NB, UTIL, false, true>), grid, dim3(NB), 0, st, e0, e1, 0, c, b, pl);
+    else MCF_LAUNCH((node_kernel<T, NB, UTIL, false, false>), grid, dim3(NB), 0, st, e0, e1, 0, c, b, pl);
 }
 
 template <typename T>
@@ -1690,13 +1702,13 @@ static void fused_go(const Consts &c, const Bufs<T> &b, const PartLayout &pl, in
     constexpr size_t VW = EPT * 64 * sizeof(double);  // LDS bytes per wave for V (and T)
     const dim3 grid(c.n);
     if (check)
-        hipExtLaunchKernelGGL((fused_kernel<T, EPT, UTIL, true, true>), grid, dim3(64 * NWC), 2 * NWC * VW, st, e0, e1,
+        MCF_LAUNCH((fused_kernel<T, EPT, UTIL, true, true>), grid, dim3(64 * NWC), 2 * NWC * VW, st, e0, e1,
                               0, c, b, pl, parity);
     else if (partial)
-        hipExtLaunchKernelGGL((fused_kernel<T, EPT, UTIL, false, true>), grid, dim3(64 * NWR), NWR * VW, st, e0, e1,
+        MCF_LAUNCH((fused_kernel<T, EPT, UTIL, false, true>), grid, dim3(64 * NWR), NWR * VW, st, e0, e1,
                               0, c, b, pl, parity);
     else
-        hipExtLaunchKernelGGL((fused_kernel<T, EPT, UTIL, false, false>), grid, dim3(64 * NWR), NWR * VW, st, e0, e1,
+        MCF_LAUNCH((fused_kernel<T, EPT, UTIL, false, false>), grid, dim3(64 * NWR), NWR * VW, st, e0, e1,
                               0, c, b, pl, parity);
 }
 
@@ -1728,10 +1740,10 @@ hipError_t launch_residual(const Consts &c, const Bufs<T> &b, const PartLayout &
 
 template <typename T>
 hipError_t launch_control(const Consts &c, const Bufs<T> &b, const PartLayout &pl, bool check, bool adapt,
-                          long long k_after, hipStream_t st)
+                          long long k_inc, hipStream_t st)
 {
     hipLaunchKernelGGL(control_kernel<T>, dim3(1), dim3(CTRL_BLOCK), 0, st, c, b, pl, check ? 1 : 0, adapt ? 1 : 0,
-                       k_after);
+                       k_inc);
     return hipGetLastError();
 }
 

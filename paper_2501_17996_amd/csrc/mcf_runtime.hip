@@ -5,7 +5,9 @@
 #include <cmath>
 #include <cstring>
 #include <deque>
+#include <map>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "mcf.h"
@@ -127,6 +129,8 @@ struct mcf_solver {
     // kernel timing of the iteration's main launches (fused, or edge + node)
     bool timing = false;
     std::vector<hipEvent_t> ev;  // pairs (start, stop) recorded during the current drive
+    // instantiated graphs of whole blocks, keyed by the block's shape (see block_key)
+    std::map<std::string, hipGraphExec_t> graphs;
     size_t ev_used = 0, ev_done = 0;
     double edge_ms = 0.0;
     long long edge_launches = 0;
@@ -334,11 +338,15 @@ int collect_events(mcf_solver *s, size_t upto)
 
 // Enqueues `count` iterations starting at iteration k0; only the last one is a check
 // iteration.  Iterations that adapt omega (k a multiple of k_adapt) or check the residual
-// write step-norm partials and end in a control launch; the others are two launches.
+// write step-norm partials and end in a control launch; the others are two launches.  Every
+// argument depends only on the block's shape (block_key): the control launches advance the
+// device's iteration count by the iterations since the previous one, and the device count is
+// k0 when the block starts (the previous block ended with a control launch).
 template <typename T>
 int enqueue_block(mcf_solver *s, long long k0, long long count)
 {
     const Bufs<T> b = s->bufs<T>();
+    long long k_ctrl = k0;  // iterations counted on the device so far
     for (long long it = 0; it < count; ++it) {
         const long long k = k0 + it;
         const bool check = it == count - 1;
@@ -360,8 +368,48 @@ int enqueue_block(mcf_solver *s, long long k0, long long count)
             MCF_TRY(launch_node<T>(s->c, b, s->pl, check, partial, s->stream, nullptr, e1));
         }
         if (check) MCF_TRY(launch_residual<T>(s->c, b, s->pl, s->sh, s->stream));
-        if (partial) MCF_TRY(launch_control<T>(s->c, b, s->pl, check, adapt, k + 1, s->stream));
+        if (partial) {
+            MCF_TRY(launch_control<T>(s->c, b, s->pl, check, adapt, k + 1 - k_ctrl, s->stream));
+            k_ctrl = k + 1;
+        }
     }
+    return MCF_OK;
+}
+
+// What makes two blocks enqueue the same launches with the same arguments: their length, the
+// buffer set their first iteration reads (fused mode), and where omega adapts.
+std::string block_key(const mcf_solver *s, long long k0, long long count)
+{
+    std::string key = std::to_string(count) + (s->parity(k0) ? "p" : "e");
+    for (long long it = 0; it < count; ++it)
+        if (adapts_at(s->c, k0 + it)) key += "," + std::to_string(it);
+    return key;
+}
+
+// Enqueues a block as one launch of its captured graph: captured on first use, then replayed.
+// Timed runs use direct launches, since their events are recorded by the dispatches themselves.
+template <typename T>
+int enqueue_block_graph(mcf_solver *s, long long k0, long long count)
+{
+    if (!s->opt.graphs || s->timing) return enqueue_block<T>(s, k0, count);
+    const std::string key = block_key(s, k0, count);
+    auto it = s->graphs.find(key);
+    if (it == s->graphs.end()) {
+        MCF_TRY(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
+        const int rc = enqueue_block<T>(s, k0, count);
+        hipGraph_t g = nullptr;
+        const hipError_t ec = hipStreamEndCapture(s->stream, &g);
+        if (rc || ec != hipSuccess || !g) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc ? rc : MCF_E_DEVICE;
+        }
+        hipGraphExec_t ex = nullptr;
+        const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ei != hipSuccess) return MCF_E_DEVICE;
+        it = s->graphs.emplace(key, ex).first;
+    }
+    MCF_TRY(hipGraphLaunch(it->second, s->stream));
     return MCF_OK;
 }
 
@@ -394,8 +442,8 @@ int drive(mcf_solver *s, long long target, bool stop_test)
     while (!stopped) {
         while (pend.size() < 2 && k_next < target) {
             const long long count = std::min(K, target - k_next);
-            rc = s->precision == MCF_FP32 ? enqueue_block<float>(s, k_next, count)
-                                          : enqueue_block<double>(s, k_next, count);
+            rc = s->precision == MCF_FP32 ? enqueue_block_graph<float>(s, k_next, count)
+                                          : enqueue_block_graph<double>(s, k_next, count);
             if (rc) return rc;
             MCF_TRY(hipMemcpyAsync(s->hs + 1 + slot, s->dsc(), sizeof(DevScalars), hipMemcpyDeviceToHost,
                                    s->stream));
@@ -489,6 +537,7 @@ void mcf_options_default(mcf_options *o)
     o->omega0 = 1.0;
     o->adapt_until = -1;
     o->device = 0;
+    o->graphs = 1;
 }
 
 size_t mcf_workspace_bytes(int32_t n, int32_t m, int32_t precision)
@@ -528,6 +577,7 @@ void mcf_destroy(mcf_solver *s)
     if (!s) return;
     if (s->pool) mcf_pool_retire(s->pool, s->pool_slot);
     if (s->stream) (void)hipStreamSynchronize(s->stream);
+    for (auto &g : s->graphs) (void)hipGraphExecDestroy(g.second);
     for (hipEvent_t e : s->ev) (void)hipEventDestroy(e);
     for (hipEvent_t e : s->blk_ev)
         if (e) (void)hipEventDestroy(e);

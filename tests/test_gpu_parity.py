@@ -327,6 +327,37 @@ def test_every_compiled_shape_matches_oracle(M, precision):
             S.close()
 
 
+@pytest.mark.parametrize("mode,precision", [(2, 1), (1, 1), (2, 0), (1, 0)])
+def test_graph_replays_equal_direct_launches(M, mode, precision):
+    """Blocks replayed from captured graphs give bitwise the iterates, scalars and stop of the
+    same blocks launched one by one: replay after replay (a block shape is captured once), with
+    status reads and state downloads between the replays, over a full solve and after a reset."""
+    inst = I.ring_instance(120, 6, seed=31)
+    kw = dict(precision=precision, kernel_mode=mode, check_every=20, tol=1e-4)
+    ref = gpu_solver(M, inst, graphs=0, **kw)
+    gra = gpu_solver(M, inst, graphs=1, **kw)
+
+    def same():
+        F1, Y1, s1 = ref.get_state()
+        F2, Y2, s2 = gra.get_state()
+        np.testing.assert_array_equal(F1, F2)
+        np.testing.assert_array_equal(Y1, Y2)
+        assert s1 == s2
+
+    for rep in range(2):
+        for blocks in (1, 3, 7):
+            a, b = ref.run(20 * blocks), gra.run(20 * blocks)
+            assert a["iters"] == b["iters"]
+            assert a["omega"] == b["omega"] and a["delta_y"] == b["delta_y"]
+            same()
+        a, b = ref.solve(), gra.solve()
+        assert a["state_name"] == b["state_name"] == "converged"
+        assert a["iters"] == b["iters"] and a["primal_obj"] == b["primal_obj"]
+        same()
+        ref.reset()
+        gra.reset()
+
+
 def test_c3_fp64_first_iterations(M):
     inst = I.config3(0)
     S = gpu_solver(M, inst)
