@@ -170,11 +170,13 @@ const char *mcf_strerror(int code);
  * j*n+i) on the device; the next iteration then reports MCF_DIVERGED. */
 int mcf_debug_poison(mcf_solver *s, int32_t which, int64_t index);
 
-/* Kernel timing for the roofline of the iteration (the single launch of a fused iteration,
- * or the edge and node launches of a two-phase one): while enabled, HIP events on the
- * solver's stream bracket those launches in every 7th iteration (7 is prime to the usual
- * check and adapt periods, so the sample keeps their mix); mcf_kernel_time returns the
- * summed milliseconds and the number of bracketed iterations since the last enable. */
+/* Kernel timing for the roofline of the iteration, on the solver's stream, while enabled.
+ * With graphs (the default) HIP events bracket each replayed block: every launch of its
+ * iterations, checks and control included.  Without, events recorded by the dispatches bracket
+ * the single launch of a fused iteration, or the edge and node launches of a two-phase one, in
+ * every 7th iteration (7 is prime to the usual check and adapt periods, so the sample keeps their
+ * mix).  mcf_kernel_time returns the summed milliseconds and the number of iterations they
+ * cover since the last enable. */
 int mcf_enable_kernel_timing(mcf_solver *s, int32_t enable);
 int mcf_kernel_time(mcf_solver *s, double *edge_ms, int64_t *edge_launches);
 

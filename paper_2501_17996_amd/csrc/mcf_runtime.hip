@@ -129,6 +129,7 @@ struct mcf_solver {
     // kernel timing of the iteration's main launches (fused, or edge + node)
     bool timing = false;
     std::vector<hipEvent_t> ev;  // pairs (start, stop) recorded during the current drive
+    std::vector<long long> ev_iters;  // iterations each pair brackets (indexed by pair)
     // instantiated graphs of whole blocks, keyed by the block's shape (see block_key)
     std::map<std::string, hipGraphExec_t> graphs;
     size_t ev_used = 0, ev_done = 0;
@@ -320,17 +321,19 @@ hipEvent_t next_event(mcf_solver *s)
         if (hipEventCreate(&e) != hipSuccess) return nullptr;
         s->ev.push_back(e);
     }
+    if (s->ev_iters.size() <= s->ev_used / 2) s->ev_iters.resize(s->ev_used / 2 + 1);
+    s->ev_iters[s->ev_used / 2] = 1;  // a pair brackets one iteration unless set otherwise
     return s->ev[s->ev_used++];
 }
 
-// Adds up the bracketed launches whose events lie in [s->ev_done, upto).
+// Adds up the bracketed iterations whose events lie in [s->ev_done, upto).
 int collect_events(mcf_solver *s, size_t upto)
 {
     for (size_t k = s->ev_done; k + 1 < upto; k += 2) {
         float ms = 0.f;
         MCF_TRY(hipEventElapsedTime(&ms, s->ev[k], s->ev[k + 1]));
         s->edge_ms += ms;
-        s->edge_launches += 1;
+        s->edge_launches += s->ev_iters[k / 2];
     }
     s->ev_done = upto;
     return MCF_OK;
@@ -343,7 +346,7 @@ int collect_events(mcf_solver *s, size_t upto)
 // device's iteration count by the iterations since the previous one, and the device count is
 // k0 when the block starts (the previous block ended with a control launch).
 template <typename T>
-int enqueue_block(mcf_solver *s, long long k0, long long count)
+int enqueue_block(mcf_solver *s, long long k0, long long count, bool sample = true)
 {
     const Bufs<T> b = s->bufs<T>();
     long long k_ctrl = k0;  // iterations counted on the device so far
@@ -355,7 +358,7 @@ int enqueue_block(mcf_solver *s, long long k0, long long count)
         // timed iterations: the dispatches themselves record the start of the first kernel and
         // the end of the last one of the iteration (no extra packets in the stream)
         hipEvent_t e0 = nullptr, e1 = nullptr;
-        const bool timed = s->timing && k % TIMING_STRIDE == 0;
+        const bool timed = sample && s->timing && k % TIMING_STRIDE == 0;
         if (timed) {
             e0 = next_event(s);
             e1 = next_event(s);
@@ -387,16 +390,17 @@ std::string block_key(const mcf_solver *s, long long k0, long long count)
 }
 
 // Enqueues a block as one launch of its captured graph: captured on first use, then replayed.
-// Timed runs use direct launches, since their events are recorded by the dispatches themselves.
+// With kernel timing on, events on the stream bracket the whole replay (every launch of the
+// block's count iterations, checks and control included).
 template <typename T>
 int enqueue_block_graph(mcf_solver *s, long long k0, long long count)
 {
-    if (!s->opt.graphs || s->timing) return enqueue_block<T>(s, k0, count);
+    if (!s->opt.graphs) return enqueue_block<T>(s, k0, count);
     const std::string key = block_key(s, k0, count);
     auto it = s->graphs.find(key);
     if (it == s->graphs.end()) {
         MCF_TRY(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
-        const int rc = enqueue_block<T>(s, k0, count);
+        const int rc = enqueue_block<T>(s, k0, count, false);
         hipGraph_t g = nullptr;
         const hipError_t ec = hipStreamEndCapture(s->stream, &g);
         if (rc || ec != hipSuccess || !g) {
@@ -409,7 +413,16 @@ int enqueue_block_graph(mcf_solver *s, long long k0, long long count)
         if (ei != hipSuccess) return MCF_E_DEVICE;
         it = s->graphs.emplace(key, ex).first;
     }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (s->timing) {
+        e0 = next_event(s);
+        e1 = next_event(s);
+        if (!e0 || !e1) return MCF_E_DEVICE;
+        s->ev_iters[(s->ev_used - 2) / 2] = count;
+        MCF_TRY(hipEventRecord(e0, s->stream));
+    }
     MCF_TRY(hipGraphLaunch(it->second, s->stream));
+    if (s->timing) MCF_TRY(hipEventRecord(e1, s->stream));
     return MCF_OK;
 }
 
@@ -468,7 +481,8 @@ int drive(mcf_solver *s, long long target, bool stop_test)
     MCF_TRY(hipStreamSynchronize(s->stream));  // drain a block queued behind a stop
     if (stopped) s->state = s->hs->state == MCF_DIVERGED ? MCF_DIVERGED : MCF_CONVERGED;
     else s->state = stop_test ? MCF_MAX_ITER : MCF_RUNNING;
-    if (s->timing && (rc = collect_events(s, s->ev_used))) return rc;
+    // blocks queued behind a stop did no work: their events are dropped
+    if (s->timing && !stopped && (rc = collect_events(s, s->ev_used))) return rc;
     s->ev_used = s->ev_done = 0;
     s->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return MCF_OK;
