@@ -139,6 +139,13 @@ int mcf_create(int32_t n, int32_t m, const int32_t *tail, const int32_t *head, c
  * whatever the outcome: read the outcome with mcf_status. */
 int mcf_solve(mcf_solver *s);
 
+/* mcf_solve without blocking: a host thread of the library runs the same solve on the handle's
+ * stream and returns.  Poll mcf_status: its state is MCF_RUNNING, with the record of the latest
+ * finished block of check_every iterations, until the solve ends.  Meanwhile every other call on
+ * the handle returns MCF_E_STATE (mcf_status and mcf_layout excepted; mcf_destroy stops the solve
+ * after its current block and waits for it).  MCF_E_STATE if a solve is already running. */
+int mcf_solve_async(mcf_solver *s);
+
 /* Runs exactly `iters` more PDHG iterations with no stop test (residual every check_every
  * iterations and at the last one).  For trajectory comparison and timing. */
 int mcf_run(mcf_solver *s, int64_t iters);
@@ -146,7 +153,7 @@ int mcf_run(mcf_solver *s, int64_t iters);
 /* Restores the cold start (F = 0, Y = I - 1 1^T, omega = omega0, k = 0) on the device. */
 int mcf_reset(mcf_solver *s);
 
-/* Copies the latest record into *out. */
+/* Copies the latest record into *out.  After an mcf_solve_async that failed, returns its error. */
 int mcf_status(const mcf_solver *s, mcf_result *out);
 
 /* Downloads the projected flow Fhat of the last checked iteration (the iterate Algorithm 2.1

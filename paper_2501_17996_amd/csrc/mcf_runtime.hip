@@ -1,13 +1,16 @@
 // libmcf host runtime: instance setup, device buffers, the iteration driver and
 // the C ABI declared in include/mcf.h.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstring>
 #include <deque>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "mcf.h"
@@ -132,6 +135,13 @@ struct mcf_solver {
     std::vector<long long> ev_iters;  // iterations each pair brackets (indexed by pair)
     // instantiated graphs of whole blocks, keyed by the block's shape (see block_key)
     std::map<std::string, hipGraphExec_t> graphs;
+    // asynchronous solve (mcf_solve_async): a host thread runs the block loop; while it runs,
+    // mcf_status reads `live` (the record of the latest finished block) under `live_mu`
+    std::thread worker;
+    std::atomic<bool> busy{false}, cancel{false};
+    int async_rc = MCF_OK;
+    mutable std::mutex live_mu;
+    mcf_result live{};
     size_t ev_used = 0, ev_done = 0;
     double edge_ms = 0.0;
     long long edge_launches = 0;
@@ -426,6 +436,31 @@ int enqueue_block_graph(mcf_solver *s, long long k0, long long count)
     return MCF_OK;
 }
 
+// The solve record of the handle's host state.
+void fill_result(const mcf_solver *s, mcf_result *r)
+{
+    const DevScalars &h = *s->hs;
+    std::memset(r, 0, sizeof(*r));
+    r->state = s->state;
+    r->checked = h.checked;
+    r->iters = s->k;
+    r->r = h.r;
+    r->r_paper = h.r_paper;
+    r->rel_primal = h.rel_primal;
+    r->rel_dual = h.rel_dual;
+    r->rel_gap = h.rel_gap;
+    r->rel_kkt = h.rel_kkt;
+    r->primal_obj = h.primal_obj;
+    r->dual_obj = h.dual_obj;
+    r->infeasible_frac = h.infeasible_frac;
+    r->omega = h.omega;
+    r->alpha = h.alpha;
+    r->beta = h.beta;
+    r->delta_f = h.dF;
+    r->delta_y = h.dY;
+    r->seconds = s->seconds;
+}
+
 // The iteration driver.  Blocks of check_every iterations end with an asynchronous copy
 // of the device scalars into a pinned snapshot slot; two blocks are kept in flight, so the
 // device never waits for the host to read a snapshot.  With stop_test the device raises
@@ -477,6 +512,12 @@ int drive(mcf_solver *s, long long target, bool stop_test)
         } else {
             s->k = r.k0 + r.count;
         }
+        if (s->busy.load(std::memory_order_relaxed)) {
+            std::lock_guard<std::mutex> lock(s->live_mu);
+            fill_result(s, &s->live);
+            s->live.state = MCF_RUNNING;
+        }
+        if (s->cancel.load(std::memory_order_relaxed)) break;  // the handle is being destroyed
     }
     MCF_TRY(hipStreamSynchronize(s->stream));  // drain a block queued behind a stop
     if (stopped) s->state = s->hs->state == MCF_DIVERGED ? MCF_DIVERGED : MCF_CONVERGED;
@@ -589,6 +630,9 @@ const char *mcf_strerror(int code)
 void mcf_destroy(mcf_solver *s)
 {
     if (!s) return;
+    // an asynchronous solve stops after its current block
+    s->cancel.store(true, std::memory_order_relaxed);
+    if (s->worker.joinable()) s->worker.join();
     if (s->pool) mcf_pool_retire(s->pool, s->pool_slot);
     if (s->stream) (void)hipStreamSynchronize(s->stream);
     for (auto &g : s->graphs) (void)hipGraphExecDestroy(g.second);
@@ -715,9 +759,21 @@ int mcf_create(int32_t n, int32_t m, const int32_t *tail, const int32_t *head, c
     return MCF_OK;
 }
 
+namespace {
+// Calls that use the handle wait for nothing: while an asynchronous solve runs they return
+// MCF_E_STATE; after it, its thread is joined first.
+int idle(mcf_solver *s)
+{
+    if (s->busy.load(std::memory_order_acquire)) return MCF_E_STATE;
+    if (s->worker.joinable()) s->worker.join();
+    return MCF_OK;
+}
+}  // namespace
+
 int mcf_reset(mcf_solver *s)
 {
     if (!s) return MCF_E_ARG;
+    if (int rc_ = idle(s)) return rc_;
     if (s->pool) return MCF_E_STATE;
     return reset_any(s);
 }
@@ -725,13 +781,42 @@ int mcf_reset(mcf_solver *s)
 int mcf_solve(mcf_solver *s)
 {
     if (!s) return MCF_E_ARG;
+    if (int rc_ = idle(s)) return rc_;
     if (s->pool) return MCF_E_STATE;
     return drive(s, s->opt.max_iter, true);
+}
+
+int mcf_solve_async(mcf_solver *s)
+{
+    if (!s) return MCF_E_ARG;
+    if (int rc = idle(s)) return rc;
+    if (s->pool) return MCF_E_STATE;
+    {
+        std::lock_guard<std::mutex> lock(s->live_mu);
+        fill_result(s, &s->live);
+        s->live.state = MCF_RUNNING;
+    }
+    s->async_rc = MCF_OK;
+    s->busy.store(true, std::memory_order_release);
+    try {
+        s->worker = std::thread([s] {
+            // the current device is per host thread
+            int rc = hipSetDevice(s->opt.device) == hipSuccess ? MCF_OK : MCF_E_DEVICE;
+            if (!rc) rc = drive(s, s->opt.max_iter, true);
+            s->async_rc = rc;
+            s->busy.store(false, std::memory_order_release);
+        });
+    } catch (...) {
+        s->busy.store(false, std::memory_order_release);
+        return MCF_E_NOMEM;
+    }
+    return MCF_OK;
 }
 
 int mcf_run(mcf_solver *s, int64_t iters)
 {
     if (!s || iters < 0) return MCF_E_ARG;
+    if (int rc_ = idle(s)) return rc_;
     if (s->pool) return MCF_E_STATE;
     int rc = pull_scalars(s);
     if (rc) return rc;
@@ -746,32 +831,19 @@ int mcf_run(mcf_solver *s, int64_t iters)
 int mcf_status(const mcf_solver *s, mcf_result *r)
 {
     if (!s || !r) return MCF_E_ARG;
-    const DevScalars &h = *s->hs;
-    std::memset(r, 0, sizeof(*r));
-    r->state = s->state;
-    r->checked = h.checked;
-    r->iters = s->k;
-    r->r = h.r;
-    r->r_paper = h.r_paper;
-    r->rel_primal = h.rel_primal;
-    r->rel_dual = h.rel_dual;
-    r->rel_gap = h.rel_gap;
-    r->rel_kkt = h.rel_kkt;
-    r->primal_obj = h.primal_obj;
-    r->dual_obj = h.dual_obj;
-    r->infeasible_frac = h.infeasible_frac;
-    r->omega = h.omega;
-    r->alpha = h.alpha;
-    r->beta = h.beta;
-    r->delta_f = h.dF;
-    r->delta_y = h.dY;
-    r->seconds = s->seconds;
-    return MCF_OK;
+    if (s->busy.load(std::memory_order_acquire)) {
+        std::lock_guard<std::mutex> lock(s->live_mu);
+        *r = s->live;
+        return MCF_OK;
+    }
+    fill_result(s, r);
+    return s->async_rc;
 }
 
 int mcf_get_solution(mcf_solver *s, double *F, double *T, double *Y)
 {
     if (!s) return MCF_E_ARG;
+    if (int rc_ = idle(s)) return rc_;
     if (s->pool) return MCF_E_STATE;
     int rc = MCF_OK;
     if (F && (rc = download_any(s, s->plan.Fhat, s->m, true, F))) return rc;
@@ -783,6 +855,7 @@ int mcf_get_solution(mcf_solver *s, double *F, double *T, double *Y)
 int mcf_get_state(mcf_solver *s, double *F, double *Y, mcf_scalars *sc)
 {
     if (!s) return MCF_E_ARG;
+    if (int rc_ = idle(s)) return rc_;
     if (s->pool) return MCF_E_STATE;
     int rc = MCF_OK;
     if (F && (rc = download_any(s, s->cur_F(), s->m, true, F))) return rc;
@@ -798,6 +871,7 @@ int mcf_get_state(mcf_solver *s, double *F, double *Y, mcf_scalars *sc)
 int mcf_set_state(mcf_solver *s, const double *F, const double *Y, const mcf_scalars *sc)
 {
     if (!s || !F) return MCF_E_ARG;
+    if (int rc_ = idle(s)) return rc_;
     if (s->pool) return MCF_E_STATE;
     if (sc && (!(sc->omega > 0.0) || sc->k < 0)) return MCF_E_ARG;
     // the uploaded state becomes buffer set 0 at iteration k (fused mode)
@@ -841,6 +915,7 @@ int mcf_set_state(mcf_solver *s, const double *F, const double *Y, const mcf_sca
 int mcf_debug_poison(mcf_solver *s, int32_t which, int64_t index)
 {
     if (!s || (which != 0 && which != 1)) return MCF_E_ARG;
+    if (int rc_ = idle(s)) return rc_;
     if (s->pool) return MCF_E_STATE;
     const int n = s->n;
     const long long cols = which == 0 ? s->m : n;
@@ -872,6 +947,7 @@ int mcf_debug_poison(mcf_solver *s, int32_t which, int64_t index)
 int mcf_enable_kernel_timing(mcf_solver *s, int32_t enable)
 {
     if (!s) return MCF_E_ARG;
+    if (int rc_ = idle(s)) return rc_;
     s->timing = enable != 0;
     s->ev_used = s->ev_done = 0;
     s->edge_ms = 0.0;
@@ -882,6 +958,7 @@ int mcf_enable_kernel_timing(mcf_solver *s, int32_t enable)
 int mcf_kernel_time(mcf_solver *s, double *edge_ms, int64_t *edge_launches)
 {
     if (!s) return MCF_E_ARG;
+    if (int rc_ = idle(s)) return rc_;
     if (edge_ms) *edge_ms = s->edge_ms;
     if (edge_launches) *edge_launches = s->edge_launches;
     return MCF_OK;
@@ -1032,6 +1109,7 @@ void mcf_pool_destroy(mcf_pool *p)
 int mcf_pool_admit(mcf_pool *p, mcf_solver *s, int32_t *slot)
 {
     if (!p || !s) return MCF_E_ARG;
+    if (int rc_ = idle(s)) return rc_;
     if (s->pool || s->precision != p->precision || !s->c.fused) return MCF_E_ARG;
     if (s->state == MCF_CONVERGED || s->state == MCF_DIVERGED) return MCF_E_STATE;
     int rc = mcf_pool_sync(p);

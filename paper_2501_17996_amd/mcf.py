@@ -30,7 +30,8 @@ MCF_KERNELS_AUTO, MCF_KERNELS_TWO_PHASE, MCF_KERNELS_FUSED = 0, 1, 2
 STATE_NAMES = {0: "running", 1: "converged", 2: "max_iter", 3: "diverged"}
 
 EXPORTED = [
-    "mcf_options_default", "mcf_workspace_bytes", "mcf_create", "mcf_solve", "mcf_run", "mcf_reset",
+    "mcf_options_default", "mcf_workspace_bytes", "mcf_create", "mcf_solve", "mcf_solve_async", "mcf_run",
+    "mcf_reset",
     "mcf_status", "mcf_get_solution", "mcf_get_state", "mcf_set_state", "mcf_destroy", "mcf_strerror",
     "mcf_debug_poison", "mcf_enable_kernel_timing", "mcf_kernel_time", "mcf_layout", "mcf_edge_shapes",
     "mcf_pool_create", "mcf_pool_admit", "mcf_pool_step", "mcf_pool_sync", "mcf_pool_poll", "mcf_pool_retire",
@@ -88,7 +89,7 @@ def lib():
         L.mcf_workspace_bytes.restype = ctypes.c_size_t
         L.mcf_create.argtypes = [ctypes.c_int32, ctypes.c_int32, _ip, _ip, _dp, ctypes.c_int32, ctypes.c_double,
                                  _dp, ctypes.POINTER(mcf_options), ctypes.POINTER(_vp)]
-        for name in ("mcf_solve", "mcf_reset"):
+        for name in ("mcf_solve", "mcf_solve_async", "mcf_reset"):
             getattr(L, name).argtypes = [_vp]
         L.mcf_run.argtypes = [_vp, ctypes.c_int64]
         L.mcf_status.argtypes = [_vp, ctypes.POINTER(mcf_result)]
@@ -161,6 +162,10 @@ def mcf_create(n, tail, head, cap, utility, gamma, w, opt: mcf_options | None = 
 
 def mcf_solve(h):
     _check(lib().mcf_solve(h), "mcf_solve")
+
+
+def mcf_solve_async(h):
+    _check(lib().mcf_solve_async(h), "mcf_solve_async")
 
 
 def mcf_run(h, iters: int):
@@ -266,6 +271,19 @@ class Solver:
     def solve(self) -> dict:
         mcf_solve(self.h)
         return self.status()
+
+    def solve_async(self):
+        """Starts the solve and returns; poll status() until its state is not "running"."""
+        mcf_solve_async(self.h)
+
+    def wait(self, poll_s: float = 1e-3) -> dict:
+        """Polls status() until an asynchronous solve has ended; returns its record."""
+        import time
+        while True:
+            st = self.status()
+            if st["state_name"] != "running":
+                return st
+            time.sleep(poll_s)
 
     def run(self, iters: int) -> dict:
         mcf_run(self.h, iters)

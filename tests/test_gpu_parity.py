@@ -358,6 +358,32 @@ def test_graph_replays_equal_direct_launches(M, mode, precision):
         gra.reset()
 
 
+def test_solve_async_equals_solve(M):
+    """mcf_solve_async runs the same solve on a library thread: polled to its end it gives the
+    blocking solve's iterations, objective and iterates bitwise.  While it runs, a call that uses
+    the handle is refused with MCF_E_STATE; destroying the handle stops it after its block."""
+    inst = I.ring_instance(150, 6, seed=41)
+    kw = dict(precision=0, tol=1e-6, check_every=20, max_iter=30000)
+    A = gpu_solver(M, inst, **kw)
+    B = gpu_solver(M, inst, **kw)
+    ref = A.solve()
+    B.solve_async()
+    with pytest.raises(M.MCFError) as ei:
+        B.get_state()
+    assert ei.value.code == M.MCF_E_STATE
+    st = B.wait()
+    assert st["state_name"] == ref["state_name"] != "running"
+    assert st["iters"] == ref["iters"] and st["primal_obj"] == ref["primal_obj"]
+    F1, Y1, s1 = A.get_state()
+    F2, Y2, s2 = B.get_state()
+    np.testing.assert_array_equal(F1, F2)
+    np.testing.assert_array_equal(Y1, Y2)
+    assert s1 == s2
+    B.reset()
+    B.solve_async()
+    B.close()
+
+
 def test_c3_fp64_first_iterations(M):
     inst = I.config3(0)
     S = gpu_solver(M, inst)
