@@ -105,10 +105,13 @@ typedef struct {
     double seconds;         /* wall time of the last mcf_solve / mcf_run call */
 } mcf_result;
 
-/* Resumable scalar state (Section 2.5 warm start): iteration k and primal weight omega. */
+/* Resumable scalar state (Section 2.5 warm start): iteration k and primal weight omega.  alpha and
+ * beta (the step sizes eta/omega and eta*omega, Section 2.4) and r (the residual of the last
+ * checked iteration) are reported by mcf_get_state; mcf_set_state reads only k and omega. */
 typedef struct {
     int64_t k;
     double omega;
+    double alpha, beta, r;
 } mcf_scalars;
 
 /* Fills *o with the defaults: tol 1e-4, REL_KKT, FP64, check_every 1, max_iter 100000,

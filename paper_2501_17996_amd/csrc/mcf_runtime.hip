@@ -864,6 +864,9 @@ int mcf_get_state(mcf_solver *s, double *F, double *Y, mcf_scalars *sc)
         if ((rc = pull_scalars(s))) return rc;
         sc->k = s->k;
         sc->omega = s->hs->omega;
+        sc->alpha = s->hs->alpha;
+        sc->beta = s->hs->beta;
+        sc->r = s->hs->r;
     }
     return MCF_OK;
 }

@@ -63,7 +63,8 @@ class mcf_result(ctypes.Structure):
 
 
 class mcf_scalars(ctypes.Structure):
-    _fields_ = [("k", ctypes.c_int64), ("omega", ctypes.c_double)]
+    _fields_ = [("k", ctypes.c_int64), ("omega", ctypes.c_double), ("alpha", ctypes.c_double),
+                ("beta", ctypes.c_double), ("r", ctypes.c_double)]
 
 
 class MCFError(RuntimeError):
@@ -192,13 +193,14 @@ def mcf_get_state(h, n: int, m: int):
     F, Y = np.empty(n * m), np.empty(n * n)
     sc = mcf_scalars()
     _check(lib().mcf_get_state(h, _ptr(F), _ptr(Y), ctypes.byref(sc)), "mcf_get_state")
-    return F, Y, {"k": int(sc.k), "omega": float(sc.omega)}
+    return F, Y, {"k": int(sc.k), "omega": float(sc.omega), "alpha": float(sc.alpha), "beta": float(sc.beta),
+                  "r": float(sc.r)}
 
 
 def mcf_set_state(h, F, Y=None, k: int | None = None, omega: float | None = None):
     F = _f64(F)
     Yk = _f64(Y) if Y is not None else None
-    sc = mcf_scalars(int(k), float(omega)) if k is not None else None
+    sc = mcf_scalars(int(k), float(omega), 0.0, 0.0, 0.0) if k is not None else None
     _check(lib().mcf_set_state(h, _ptr(F), _ptr(Yk) if Yk is not None else None,
                                ctypes.byref(sc) if sc is not None else None), "mcf_set_state")
 

@@ -379,6 +379,11 @@ def test_solve_async_equals_solve(M):
     np.testing.assert_array_equal(F1, F2)
     np.testing.assert_array_equal(Y1, Y2)
     assert s1 == s2
+    # the reported step sizes are eta/omega and eta*omega (Section 2.4), r the last check's residual
+    eta = oracle.OracleSolver(inst).eta
+    assert s1["alpha"] == pytest.approx(eta / s1["omega"], rel=1e-15)
+    assert s1["beta"] == pytest.approx(eta * s1["omega"], rel=1e-15)
+    assert s1["r"] == ref["r"]
     B.reset()
     B.solve_async()
     B.close()
