@@ -195,17 +195,19 @@ def test_cf1_two_nodes(orc, utility):
     assert abs(M["primal_obj"] - M["dual_obj"]) < 1e-6 * (1 + abs(M["primal_obj"]))
 
 
-@pytest.mark.parametrize("utility,n", [(0, 5), (0, 7), (1, 5), (1, 6), (2, 5), (2, 6)])
-def test_cf2_ring(orc, utility, n):
+@pytest.mark.parametrize("utility,n,gamma", [(0, 5, 0.0), (0, 7, 0.0), (1, 5, 0.5), (1, 6, 0.5), (1, 6, 0.3),
+                                             (2, 5, 2.0), (2, 6, 2.0)])
+def test_cf2_ring(orc, utility, n, gamma):
     """Directed ring, uniform c and w: with hop distance d = (i - j) mod n,
-    log: T_ij = c / ((n-1) d);  power(1/2): T_ij = c / (H_{n-1} d^2);
-    alpha-fair: T_ij = c d^(-1/a) / sum_d d^(1-1/a) (u'(T_d) proportional to d, sum_d d T_d = c)."""
+    log: T_ij = c / ((n-1) d);  power(gamma): T_ij = c d^(-1/(1-gamma)) / sum_d d^(-gamma/(1-gamma)),
+    c / (H_{n-1} d^2) at gamma = 1/2;  alpha-fair: T_ij = c d^(-1/a) / sum_d d^(1-1/a)
+    (in every case u'(T_d) is proportional to d and sum_d d T_d = c)."""
     c, w = 1.3, 0.8
     tail = np.arange(n)
     head = (tail + 1) % n
     W = np.full((n, n), w)
     np.fill_diagonal(W, 0)
-    inst = _inst(n, tail, head, np.full(n, c), W, utility=utility, gamma=GAMMA[utility])
+    inst = _inst(n, tail, head, np.full(n, c), W, utility=utility, gamma=gamma)
     s = _solve_tight(orc, inst)
     _, Th, _ = _last_math(s, inst)
     H = sum(1.0 / d for d in range(1, n))
@@ -216,11 +218,12 @@ def test_cf2_ring(orc, utility, n):
             d = (i - j) % n
             if utility == 0:
                 expect = c / ((n - 1) * d)
-            elif utility == 1:
+            elif utility == 1 and gamma == 0.5:
                 expect = c / (H * d * d)
+            elif utility == 1:
+                expect = c * d ** (-1 / (1 - gamma)) / sum(e ** (-gamma / (1 - gamma)) for e in range(1, n))
             else:
-                a = GAMMA[2]
-                expect = c * d ** (-1 / a) / sum(e ** (1 - 1 / a) for e in range(1, n))
+                expect = c * d ** (-1 / gamma) / sum(e ** (1 - 1 / gamma) for e in range(1, n))
             assert Th[i, j] == pytest.approx(expect, rel=1e-6)
 
 
