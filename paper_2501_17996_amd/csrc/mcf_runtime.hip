@@ -24,6 +24,7 @@ constexpr int MAX_N = 16384;
 // kernel timing brackets the dominant launch of every TIMING_STRIDE-th iteration (a stride
 // prime to check_every and k_adapt samples the same mix of iteration kinds)
 constexpr long long TIMING_STRIDE = 7;
+constexpr size_t MAX_GRAPHS = 32;  // captured block shapes kept per handle
 constexpr size_t ALIGN = 256;
 
 size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
@@ -408,6 +409,9 @@ int enqueue_block_graph(mcf_solver *s, long long k0, long long count)
     if (!s->opt.graphs) return enqueue_block<T>(s, k0, count);
     const std::string key = block_key(s, k0, count);
     auto it = s->graphs.find(key);
+    // a solve uses two or three block shapes; runs of many different lengths go out directly
+    // once the cache holds MAX_GRAPHS of them
+    if (it == s->graphs.end() && s->graphs.size() >= MAX_GRAPHS) return enqueue_block<T>(s, k0, count);
     if (it == s->graphs.end()) {
         MCF_TRY(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
         const int rc = enqueue_block<T>(s, k0, count, false);

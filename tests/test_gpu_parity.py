@@ -358,6 +358,24 @@ def test_graph_replays_equal_direct_launches(M, mode, precision):
         gra.reset()
 
 
+def test_graph_cache_past_its_bound(M):
+    """Runs of every length from 1 to 45 make more block shapes than the per-handle graph cache
+    keeps: the shapes past the bound go out directly, and the results stay bitwise those of a
+    handle without graphs."""
+    inst = I.ring_instance(90, 5, seed=33)
+    kw = dict(precision=1, kernel_mode=2, check_every=20, tol=1e-12)
+    ref = gpu_solver(M, inst, graphs=0, **kw)
+    gra = gpu_solver(M, inst, graphs=1, **kw)
+    for L in range(1, 46):
+        a, b = ref.run(L), gra.run(L)
+        assert a["iters"] == b["iters"]
+    F1, Y1, s1 = ref.get_state()
+    F2, Y2, s2 = gra.get_state()
+    np.testing.assert_array_equal(F1, F2)
+    np.testing.assert_array_equal(Y1, Y2)
+    assert s1 == s2
+
+
 def test_solve_async_equals_solve(M):
     """mcf_solve_async runs the same solve on a library thread: polled to its end it gives the
     blocking solve's iterations, objective and iterates bitwise.  While it runs, a call that uses
