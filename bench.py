@@ -367,7 +367,7 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    # events on the stream bracket every replayed block of the timed steps (kernel roofline)
+    # a pair of stream events spans each timed step (kernel roofline)
     mcf.mcf_enable_kernel_timing(S.h, True)
     iters = 0
     t0 = time.perf_counter()
@@ -410,8 +410,8 @@ def main():
                      "kernel": "fused iteration" if fused else "edge + node phases (one iteration)",
                      "avg_launch_us": edge_ms * 1e3 / max(1, launches),
                      "launches": launches,
-                     "events": "on the solver's stream around every replayed graph of the timed steps (a block of "
-                               "check_every iterations: all its launches, checks and control included)"},
+                     "events": "on the solver's stream around each timed step (every launch of its iterations, "
+                               "checks and control included; blocks replayed from captured graphs)"},
     }
     if args.workload == "c2" and args.iters == 0 and not args.no_large:
         S.close()

@@ -181,8 +181,8 @@ const char *mcf_strerror(int code);
 int mcf_debug_poison(mcf_solver *s, int32_t which, int64_t index);
 
 /* Kernel timing for the roofline of the iteration, on the solver's stream, while enabled.
- * With graphs (the default) HIP events bracket each replayed block: every launch of its
- * iterations, checks and control included.  Without, events recorded by the dispatches bracket
+ * With graphs (the default) one pair of HIP events spans each mcf_solve / mcf_run: every launch
+ * of its iterations, checks and control included.  Without, events recorded by the dispatches bracket
  * the single launch of a fused iteration, or the edge and node launches of a two-phase one, in
  * every 7th iteration (7 is prime to the usual check and adapt periods, so the sample keeps their
  * mix).  mcf_kernel_time returns the summed milliseconds and the number of iterations they

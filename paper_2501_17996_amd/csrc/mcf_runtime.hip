@@ -401,8 +401,6 @@ std::string block_key(const mcf_solver *s, long long k0, long long count)
 }
 
 // Enqueues a block as one launch of its captured graph: captured on first use, then replayed.
-// With kernel timing on, events on the stream bracket the whole replay (every launch of the
-// block's count iterations, checks and control included).
 template <typename T>
 int enqueue_block_graph(mcf_solver *s, long long k0, long long count)
 {
@@ -427,16 +425,7 @@ int enqueue_block_graph(mcf_solver *s, long long k0, long long count)
         if (ei != hipSuccess) return MCF_E_DEVICE;
         it = s->graphs.emplace(key, ex).first;
     }
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (s->timing) {
-        e0 = next_event(s);
-        e1 = next_event(s);
-        if (!e0 || !e1) return MCF_E_DEVICE;
-        s->ev_iters[(s->ev_used - 2) / 2] = count;
-        MCF_TRY(hipEventRecord(e0, s->stream));
-    }
     MCF_TRY(hipGraphLaunch(it->second, s->stream));
-    if (s->timing) MCF_TRY(hipEventRecord(e1, s->stream));
     return MCF_OK;
 }
 
@@ -488,9 +477,17 @@ int drive(mcf_solver *s, long long target, bool stop_test)
     const long long K = std::max(1, s->opt.check_every);
     std::deque<Pending> pend;
     long long k_next = s->k;
+    const long long k_start = s->k;
     int slot = 0;
     s->ev_used = s->ev_done = 0;
     bool stopped = s->hs->stop != 0;
+    // kernel timing with graphs: one pair of stream events around everything the drive enqueues
+    const bool span_timing = s->timing && s->opt.graphs && !stopped;
+    if (span_timing) {
+        hipEvent_t e0 = next_event(s);
+        if (!e0) return MCF_E_DEVICE;
+        MCF_TRY(hipEventRecord(e0, s->stream));
+    }
     while (!stopped) {
         while (pend.size() < 2 && k_next < target) {
             const long long count = std::min(K, target - k_next);
@@ -509,7 +506,7 @@ int drive(mcf_solver *s, long long target, bool stop_test)
         pend.pop_front();
         MCF_TRY(hipEventSynchronize(s->blk_ev[r.slot]));
         *s->hs = s->hs[1 + r.slot];
-        if (s->timing && (rc = collect_events(s, r.ev_end))) return rc;
+        if (s->timing && !span_timing && (rc = collect_events(s, r.ev_end))) return rc;
         if (s->hs->stop) {
             s->k = s->hs->k;  // the launches after the stop did nothing
             stopped = true;
@@ -523,11 +520,23 @@ int drive(mcf_solver *s, long long target, bool stop_test)
         }
         if (s->cancel.load(std::memory_order_relaxed)) break;  // the handle is being destroyed
     }
+    if (span_timing) {
+        hipEvent_t e1 = next_event(s);
+        if (!e1) return MCF_E_DEVICE;
+        MCF_TRY(hipEventRecord(e1, s->stream));
+    }
     MCF_TRY(hipStreamSynchronize(s->stream));  // drain a block queued behind a stop
     if (stopped) s->state = s->hs->state == MCF_DIVERGED ? MCF_DIVERGED : MCF_CONVERGED;
     else s->state = stop_test ? MCF_MAX_ITER : MCF_RUNNING;
-    // blocks queued behind a stop did no work: their events are dropped
-    if (s->timing && !stopped && (rc = collect_events(s, s->ev_used))) return rc;
+    if (span_timing) {
+        // the span covers the iterations done (and the few launches queued behind a stop, which
+        // return at entry)
+        s->ev_iters[0] = s->k - k_start;
+        if ((rc = collect_events(s, s->ev_used))) return rc;
+    } else if (s->timing && !stopped && (rc = collect_events(s, s->ev_used))) {
+        // without graphs, sampled iterations queued behind a stop did no work: they are dropped
+        return rc;
+    }
     s->ev_used = s->ev_done = 0;
     s->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return MCF_OK;
