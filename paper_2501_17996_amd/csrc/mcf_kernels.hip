@@ -625,7 +625,8 @@ __global__ __launch_bounds__(WPE == 1 ? 256 : 64 * WPE) void edge_kernel(Consts 
 // iterate type, in its edge order); the sums are then added over the waves in wave order
 // through LDS into Sout[:,t].  Partials per tail: wave totals added in wave order.
 template <typename T, int NV, bool CHECK, bool PARTIAL>
-__global__ __launch_bounds__(64 * EDGE_PAR_WAVES) void edge_kernel_par(Consts c, Bufs<T> b, PartLayout pl)
+__global__ __launch_bounds__(64 * EDGE_PAR_WAVES) __attribute__((amdgpu_waves_per_eu(NV == 4 && !CHECK ? 6 : 1)))
+void edge_kernel_par(Consts c, Bufs<T> b, PartLayout pl)
 {
     constexpr int VEC = Vec<T>::N;
     constexpr int NW = EDGE_PAR_WAVES;
@@ -642,11 +643,16 @@ __global__ __launch_bounds__(64 * EDGE_PAR_WAVES) void edge_kernel_par(Consts c,
     const T *yt = b.Y + (long long)tn * ld;
     const double rho = c.rho, omr = 1.0 - c.rho;
     const int e0 = b.out_off[tn], e1 = b.out_off[tn + 1];
-    T so[NV][VEC];
+    // this wave's out-edge sum lives in its own slice of sol (registers are what limit how many
+    // workgroups a CU holds; each lane touches only its own entries until the barrier)
+    T *so = sol + w * COL + t * VEC;
+    {
+        T z[VEC];
 #pragma unroll
-    for (int v = 0; v < NV; ++v)
+        for (int u = 0; u < VEC; ++u) z[u] = T(0);
 #pragma unroll
-        for (int u = 0; u < VEC; ++u) so[v][u] = T(0);
+        for (int v = 0; v < NV; ++v) vstore(so + v * 64 * VEC, z);
+    }
     double dF_w = 0.0, e_w = 0.0, sup_w = 0.0;
     for (int e = e0 + w; e < e1; e += NW) {
         const T *yh = b.Y + (long long)__builtin_amdgcn_readfirstlane(b.head[e]) * ld;
@@ -723,7 +729,8 @@ __global__ __launch_bounds__(64 * EDGE_PAR_WAVES) void edge_kernel_par(Consts c,
         for (int v = 0; v < NV; ++v) {
             const int i = (v * 64 + t) * VEC;
             if (i < n) {
-                T fn[VEC], fhv[VEC], dv[VEC];
+                T fn[VEC], fhv[VEC], dv[VEC], acc[VEC];
+                vload(so + v * 64 * VEC, acc);
 #pragma unroll
                 for (int u = 0; u < VEC; ++u) {
                     T fov = fo[v][u];
@@ -731,7 +738,7 @@ __global__ __launch_bounds__(64 * EDGE_PAR_WAVES) void edge_kernel_par(Consts c,
                     const double fod = (double)fov;
                     const double fh = fmax((double)q[v][u] - mu, 0.0);
                     fn[u] = (T)(rho * fh + omr * fod);
-                    so[v][u] += fn[u];
+                    acc[u] += fn[u];
                     if (PARTIAL) {
                         const double d = (double)fn[u] - fod;
                         dsum += d * d;
@@ -742,6 +749,7 @@ __global__ __launch_bounds__(64 * EDGE_PAR_WAVES) void edge_kernel_par(Consts c,
                         esum += (double)dv[u] * (double)dv[u];
                     }
                 }
+                vstore(so + v * 64 * VEC, acc);
                 vstore_nt(f + i, fn);
                 if (CHECK) {
                     vstore_nt(b.Fhat + (long long)e * ld + i, fhv);
@@ -763,9 +771,6 @@ __global__ __launch_bounds__(64 * EDGE_PAR_WAVES) void edge_kernel_par(Consts c,
         if (CHECK) sup_w += cap * fmax(gmax, 0.0);  // c_l (max_i (Y A)_il)_+
     }
     // out-edge sums over the waves, in wave order
-#pragma unroll
-    for (int v = 0; v < NV; ++v)
-        vstore(sol + w * COL + (v * 64 + t) * VEC, so[v]);
     if (t == 0) {
         red[w] = dF_w;
         red[NW + w] = e_w;
