@@ -50,6 +50,9 @@ constexpr int FUSED_MAX_N = 512;
 constexpr int FUSED_INC_CHUNK = 256;
 // Edges (one wave each) per block of the residual pass.
 constexpr int RES_EDGES = 16;
+// Entries (edge 0) past the end of the device in-edge list, so that the node phase can load a
+// whole batch of edge ids at once.
+constexpr int IN_EDGE_PAD = 16;
 
 // Offsets (in doubles) of the partial-sum segments.
 struct PartLayout {

@@ -803,17 +803,25 @@ void edge_kernel_par(Consts c, Bufs<T> b, PartLayout pl)
 // -------------------------------------------------------------- node phase
 // Grid (ceil(n/NB), n): thread (x, j) owns entry i of node column j.  Gathers over the
 // CSR edge lists accumulate in FP64 in list order.  Loads are issued sixteen edges at a time
-// and unconditionally (a slot past the list end reloads its last edge and adds nothing), so a
-// node with up to 16 edges in a list costs one round trip to memory.
+// and unconditionally (a slot past the list end reloads the batch's first edge and adds
+// nothing), so a node with up to 16 edges in a list costs one round trip to memory.  The
+// sixteen edge ids of a batch are one scalar load: the in-edge list carries IN_EDGE_PAD
+// entries past its end, so the load never leaves it.
 template <typename T>
 __device__ __forceinline__ double gather_in(const T *X, const int *in_edge, int i0, int i1, long long ld, int i)
 {
     constexpr int B = 16;
+    static_assert(B <= IN_EDGE_PAD, "a batch of edge ids may read past the list end");
+    typedef const __attribute__((address_space(4))) int cint;
     double v = 0.0;
     for (int k = i0; k < i1; k += B) {
+        int id[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u) id[u] = ((cint *)in_edge)[k + u];
         T a[B];
 #pragma unroll
-        for (int u = 0; u < B; ++u) a[u] = X[(long long)in_edge[k + u < i1 ? k + u : i1 - 1] * ld + i];
+        for (int u = 0; u < B; ++u) a[u] = X[(long long)(k + u < i1 ? id[u] : id[0]) * ld + i];
+        __builtin_amdgcn_sched_barrier(0);  // all B loads in flight before the first add waits
 #pragma unroll
         for (int u = 0; u < B; ++u)
             if (k + u < i1) v += (double)a[u];
@@ -860,13 +868,16 @@ __global__ __launch_bounds__(NB) void node_kernel(Consts c, Bufs<T> b, PartLayou
     if (i < c.n) {
         const int i0 = b.in_off[j], i1 = b.in_off[j + 1];
         const long long x = (long long)j * ld + i;
+        // this entry's own operands first, so that their loads are in flight during the gather
+        // (after the store to P the compiler could not move them above it)
+        const T sout = b.Sout[x], pot = b.P[x], yt = b.Y[x], wt = b.W[x];
         // P' = F_new A^T; V = Fbar A^T = (2/rho) P' - ((2 - rho)/rho) P
-        const double pn = p_entry<T>(b.F, b.in_edge, i0, i1, b.Sout[x], ld, i);
-        const double po = (double)b.P[x];
+        const double pn = p_entry<T>(b.F, b.in_edge, i0, i1, sout, ld, i);
+        const double po = (double)pot;
         b.P[x] = (T)pn;
         const double v = (2.0 / c.rho) * pn - ((2.0 - c.rho) / c.rho) * po;
-        const double y = (double)b.Y[x];
-        const double w = (double)b.W[x];
+        const double y = (double)yt;
+        const double w = (double)wt;
         const double yhat = (i != j) ? prox_dual<UTIL>(y - beta * v, beta, w, g, c.c1, -y) : 0.0;
         const T yn = (T)(c.rho * yhat + (1.0 - c.rho) * y);
         b.Y[x] = yn;

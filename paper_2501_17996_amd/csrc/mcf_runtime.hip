@@ -92,7 +92,7 @@ Plan make_plan(int n, int m, int precision, bool fused, int node_block)
     p.head = take((size_t)m * 4);
     p.out_off = take((size_t)(n + 1) * 4);
     p.in_off = take((size_t)(n + 1) * 4);
-    p.in_edge = take((size_t)m * 4);
+    p.in_edge = take((size_t)(m + IN_EDGE_PAD) * 4);
     p.inc_off = take(fused ? (size_t)(n + 1) * 4 : 0);
     p.inc = take(fused ? (size_t)m * 2 * 8 : 0);
     p.part = take((size_t)pl.total * 8);
@@ -234,7 +234,7 @@ int upload_problem(mcf_solver *s, const int *tail, const int *head, const double
         if (head[a] != head[b]) return head[a] < head[b];
         return a < b;
     });
-    std::vector<int> t(m), h(m), out_off(n + 1, 0), in_off(n + 1, 0), in_edge(m);
+    std::vector<int> t(m), h(m), out_off(n + 1, 0), in_off(n + 1, 0), in_edge(m + IN_EDGE_PAD, 0);
     std::vector<double> c(m);
     for (int e = 0; e < m; ++e) {
         t[e] = tail[perm[e]];
@@ -272,7 +272,7 @@ int upload_problem(mcf_solver *s, const int *tail, const int *head, const double
     MCF_TRY(hipMemcpyAsync(b + p.head, h.data(), m * 4, hipMemcpyHostToDevice, st));
     MCF_TRY(hipMemcpyAsync(b + p.out_off, out_off.data(), (n + 1) * 4, hipMemcpyHostToDevice, st));
     MCF_TRY(hipMemcpyAsync(b + p.in_off, in_off.data(), (n + 1) * 4, hipMemcpyHostToDevice, st));
-    MCF_TRY(hipMemcpyAsync(b + p.in_edge, in_edge.data(), m * 4, hipMemcpyHostToDevice, st));
+    MCF_TRY(hipMemcpyAsync(b + p.in_edge, in_edge.data(), in_edge.size() * 4, hipMemcpyHostToDevice, st));
     // per-node incidence list of the fused iteration: entering edges, then leaving edges
     std::vector<int> inc_off(n + 1, 0);
     std::vector<int2> inc((size_t)2 * m);
