@@ -34,6 +34,7 @@ struct Consts {
     int fused;             // 1: node-centric single-launch iteration (n <= FUSED_MAX_N)
     int nep, nnp;          // partials per edge quantity (dF, e, sup; one per tail node) and per node quantity
     int edge_par;          // 1: out-edge sums grouped by wave (concurrent edge phase)
+    int node_latency;      // 1: regular node launches in the latency form (F within NODE_LATENCY_BYTES)
     int nrp;               // partials of the residual pass (a, b; one per RES_EDGES edges)
 };
 
@@ -53,6 +54,12 @@ constexpr int RES_EDGES = 16;
 // Entries (edge 0) past the end of the device in-edge list, so that the node phase can load a
 // whole batch of edge ids at once.
 constexpr int IN_EDGE_PAD = 16;
+// Largest F (bytes) for which the regular node launch takes its latency form: all of a
+// thread's loads in flight at once.  Such an F stays largely in the 256 MB Infinity Cache, where
+// latency bounds the launch; beyond it the launch streams from HBM and the form that keeps
+// fewer loads in flight per wave is measurably faster (crossover between n = 3000 and 4096 at
+// out-degree 10 in FP32).
+constexpr long long NODE_LATENCY_BYTES = 512ll << 20;
 
 // Offsets (in doubles) of the partial-sum segments.
 struct PartLayout {

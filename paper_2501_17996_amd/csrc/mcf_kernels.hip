@@ -803,11 +803,13 @@ void edge_kernel_par(Consts c, Bufs<T> b, PartLayout pl)
 // -------------------------------------------------------------- node phase
 // Grid (ceil(n/NB), n): thread (x, j) owns entry i of node column j.  Gathers over the
 // CSR edge lists accumulate in FP64 in list order.  Loads are issued sixteen edges at a time
-// and unconditionally (a slot past the list end reloads the batch's first edge and adds
-// nothing), so a node with up to 16 edges in a list costs one round trip to memory.  The
-// sixteen edge ids of a batch are one scalar load: the in-edge list carries IN_EDGE_PAD
-// entries past its end, so the load never leaves it.
-template <typename T>
+// and unconditionally (a slot past the list end reloads an edge of the list and adds nothing),
+// so a node with up to 16 edges in a list costs one round trip to memory.
+// WIDE (the latency form): the sixteen edge ids of a batch are one scalar load (the in-edge
+// list carries IN_EDGE_PAD entries past its end, so the load never leaves it) and all sixteen
+// column loads are issued before the first add waits.  Otherwise each id is loaded on its own
+// and the compiler interleaves the column loads with the adds, fewer of them in flight.
+template <typename T, bool WIDE = false>
 __device__ __forceinline__ double gather_in(const T *X, const int *in_edge, int i0, int i1, long long ld, int i)
 {
     constexpr int B = 16;
@@ -815,13 +817,18 @@ __device__ __forceinline__ double gather_in(const T *X, const int *in_edge, int 
     typedef const __attribute__((address_space(4))) int cint;
     double v = 0.0;
     for (int k = i0; k < i1; k += B) {
-        int id[B];
-#pragma unroll
-        for (int u = 0; u < B; ++u) id[u] = ((cint *)in_edge)[k + u];
         T a[B];
+        if (WIDE) {
+            int id[B];
 #pragma unroll
-        for (int u = 0; u < B; ++u) a[u] = X[(long long)(k + u < i1 ? id[u] : id[0]) * ld + i];
-        __builtin_amdgcn_sched_barrier(0);  // all B loads in flight before the first add waits
+            for (int u = 0; u < B; ++u) id[u] = ((cint *)in_edge)[k + u];
+#pragma unroll
+            for (int u = 0; u < B; ++u) a[u] = X[(long long)(k + u < i1 ? id[u] : id[0]) * ld + i];
+            __builtin_amdgcn_sched_barrier(0);
+        } else {
+#pragma unroll
+            for (int u = 0; u < B; ++u) a[u] = X[(long long)in_edge[k + u < i1 ? k + u : i1 - 1] * ld + i];
+        }
 #pragma unroll
         for (int u = 0; u < B; ++u)
             if (k + u < i1) v += (double)a[u];
@@ -847,13 +854,14 @@ __device__ __forceinline__ double gather_out(const T *X, int o0, int o1, long lo
 
 // (F A^T)_ij = sum_{l in in(j)} F_il - sum_{l in out(j)} F_il with the out-edge sum first
 // rounded to the iterate type, exactly as the edge phase stages it in Sout.
-template <typename T>
+template <typename T, bool WIDE = false>
 __device__ __forceinline__ double p_entry(const T *X, const int *in_edge, int i0, int i1, T sout, long long ld, int i)
 {
-    return gather_in<T>(X, in_edge, i0, i1, ld, i) - (double)sout;
+    return gather_in<T, WIDE>(X, in_edge, i0, i1, ld, i) - (double)sout;
 }
 
-template <typename T, int NB, int UTIL, bool CHECK, bool PARTIAL>
+// LAT: the latency form (regular launches of instances whose F is within NODE_LATENCY_BYTES).
+template <typename T, int NB, int UTIL, bool CHECK, bool PARTIAL, bool LAT>
 __global__ __launch_bounds__(NB) void node_kernel(Consts c, Bufs<T> b, PartLayout pl)
 {
     constexpr int NW = NB / 64;
@@ -868,16 +876,25 @@ __global__ __launch_bounds__(NB) void node_kernel(Consts c, Bufs<T> b, PartLayou
     if (i < c.n) {
         const int i0 = b.in_off[j], i1 = b.in_off[j + 1];
         const long long x = (long long)j * ld + i;
-        // this entry's own operands first, so that their loads are in flight during the gather
-        // (after the store to P the compiler could not move them above it)
-        const T sout = b.Sout[x], pot = b.P[x], yt = b.Y[x], wt = b.W[x];
         // P' = F_new A^T; V = Fbar A^T = (2/rho) P' - ((2 - rho)/rho) P
-        const double pn = p_entry<T>(b.F, b.in_edge, i0, i1, sout, ld, i);
-        const double po = (double)pot;
-        b.P[x] = (T)pn;
+        double pn, po, y, w;
+        if (LAT) {
+            // this entry's own operands first, so that their loads are in flight during the
+            // gather (after the store to P the compiler could not move them above it)
+            const T sout = b.Sout[x], pot = b.P[x], yt = b.Y[x], wt = b.W[x];
+            pn = p_entry<T, true>(b.F, b.in_edge, i0, i1, sout, ld, i);
+            po = (double)pot;
+            y = (double)yt;
+            w = (double)wt;
+            b.P[x] = (T)pn;
+        } else {
+            pn = p_entry<T>(b.F, b.in_edge, i0, i1, b.Sout[x], ld, i);
+            po = (double)b.P[x];
+            b.P[x] = (T)pn;
+            y = (double)b.Y[x];
+            w = (double)b.W[x];
+        }
         const double v = (2.0 / c.rho) * pn - ((2.0 - c.rho) / c.rho) * po;
-        const double y = (double)yt;
-        const double w = (double)wt;
         const double yhat = (i != j) ? prox_dual<UTIL>(y - beta * v, beta, w, g, c.c1, -y) : 0.0;
         const T yn = (T)(c.rho * yhat + (1.0 - c.rho) * y);
         b.Y[x] = yn;
@@ -1689,9 +1706,10 @@ static void node_go(const Consts &c, const Bufs<T> &b, const PartLayout &pl, boo
                     hipEvent_t e0, hipEvent_t e1)
 {
     const dim3 grid((c.n + NB - 1) / NB, c.n);
-    if (check) MCF_LAUNCH((node_kernel<T, NB, UTIL, true, true>), grid, dim3(NB), 0, st, e0, e1, 0, c, b, pl);
-    else if (partial) MCF_LAUNCH((node_kernel<T, NB, UTIL, false, true>), grid, dim3(NB), 0, st, e0, e1, 0, c, b, pl);
-    else MCF_LAUNCH((node_kernel<T, NB, UTIL, false, false>), grid, dim3(NB), 0, st, e0, e1, 0, c, b, pl);
+    if (check) MCF_LAUNCH((node_kernel<T, NB, UTIL, true, true, false>), grid, dim3(NB), 0, st, e0, e1, 0, c, b, pl);
+    else if (partial) MCF_LAUNCH((node_kernel<T, NB, UTIL, false, true, false>), grid, dim3(NB), 0, st, e0, e1, 0, c, b, pl);
+    else if (c.node_latency) MCF_LAUNCH((node_kernel<T, NB, UTIL, false, false, true>), grid, dim3(NB), 0, st, e0, e1, 0, c, b, pl);
+    else MCF_LAUNCH((node_kernel<T, NB, UTIL, false, false, false>), grid, dim3(NB), 0, st, e0, e1, 0, c, b, pl);
 }
 
 template <typename T>
