@@ -5,7 +5,8 @@ node-phase block (64 and 256 threads), on a ring + chords instance of out-degree
 of the larger workloads) at a ladder of sizes n, for FP32 and FP64 iterates, and writes the
 fastest pair per size into ``csrc/tuned_shapes.inc``.  That table is compiled into libmcf.so:
 an entry covers every n up to its size above the previous entry's, so the shape is a function of
-(n, precision) alone and a solve never depends on timing.  Rebuild the library after running.
+(n, precision) alone and a solve never depends on timing.  Entries of sizes not measured in a run
+are kept from the existing table.  Rebuild the library after running.
 
 A candidate's time is the mean duration of its regular iterations (edge and node launches),
 from the events the dispatches record (``mcf_enable_kernel_timing``), after warm-up iterations.
@@ -16,6 +17,7 @@ from __future__ import annotations
 
 import argparse
 import os
+import re
 import sys
 import time
 
@@ -71,20 +73,37 @@ def tune(sizes, log=print):
     return results
 
 
+ENTRY = re.compile(r"^\s*\{(\d+), (\d+), \{(\d+), (\d+), (\d+)\}, (\d+)\},\s*//\s*([0-9.]+) us")
+
+
+def read_inc(path=INC):
+    """The entries of an existing table: {(bytes, n_max): (waves, vectors, par, node_block, us)}."""
+    out = {}
+    if os.path.exists(path):
+        for line in open(path):
+            m = ENTRY.match(line)
+            if m:
+                b, n, w, v, par, nb = (int(m.group(k)) for k in range(1, 7))
+                out[(b, n)] = (w, v, par, nb, float(m.group(7)))
+    return out
+
+
 def write_inc(results, sizes, path=INC):
+    entries = read_inc(path)
+    for precision in (1, 0):
+        for n in sizes:
+            rows = results.get((precision, n))
+            if rows:
+                ms, waves, vectors, nb = rows[0]
+                entries[(4 if precision else 8, n)] = (waves, vectors, 1 if waves == 1 else 0, nb, ms * 1e3)
     lines = ["// Two-phase launch shapes by measurement, written by paper_2501_17996_amd/tune.py on one",
              "// MI355X (ring + chords instances of out-degree 10; mean regular-iteration time of the",
              "// edge and node launches).  Entries ascend in n_max per iterate size.",
              "static const TunedEntry TUNED_SHAPES[] = {"]
-    for precision in (1, 0):
-        for n in sizes:
-            rows = results.get((precision, n))
-            if not rows:
-                continue
-            ms, waves, vectors, nb = rows[0]
-            par = 1 if waves == 1 else 0
-            lines.append(f"    {{{4 if precision else 8}, {n}, {{{waves}, {vectors}, {par}}}, {nb}}},"
-                         f"  // {ms * 1e3:.2f} us")
+    for b in (4, 8):
+        for n in sorted(k[1] for k in entries if k[0] == b):
+            w, v, par, nb, us = entries[(b, n)]
+            lines.append(f"    {{{b}, {n}, {{{w}, {v}, {par}}}, {nb}}},  // {us:.2f} us")
     lines.append("};")
     with open(path, "w") as f:
         f.write("\n".join(lines) + "\n")
