@@ -86,6 +86,13 @@ typedef struct {
      * by one.  Results are the same either way.  Kernel timing (mcf_enable_kernel_timing) always
      * launches directly. */
     int32_t graphs;
+    /* Form of the regular two-phase node launch: 0 (default) = chosen from the size of F (the
+     * latency form while F is at most 512 MiB, else the streaming form); 1 = latency form (the
+     * entry's own operands and a whole batch of in-edge loads in flight at once); 2 = streaming
+     * form (fewer loads in flight per wave).  Other values: MCF_E_ARG.  The two forms compute the
+     * same quantities from the same source expressions and each is deterministic; iterates of the
+     * two have been seen to differ in the last bits. */
+    int32_t node_form;
 } mcf_options;
 
 /* Latest solve record.  Residuals are those of the last checked iteration:

@@ -684,6 +684,7 @@ int mcf_create(int32_t n, int32_t m, const int32_t *tail, const int32_t *head, c
         shape = want;
     }
     int node_block = node_block_for(n, bytes);
+    if (o.node_form < 0 || o.node_form > 2) return MCF_E_ARG;
     if (o.node_block != 0) {
         if (o.node_block != 64 && o.node_block != 256) return MCF_E_ARG;
         node_block = o.node_block;
@@ -730,7 +731,9 @@ int mcf_create(int32_t n, int32_t m, const int32_t *tail, const int32_t *head, c
     c.node_block = node_block;
     c.fused = fused ? 1 : 0;
     c.edge_par = s->sh.par;
-    c.node_latency = (long long)n * m * (o.precision == MCF_FP32 ? 4 : 8) <= NODE_LATENCY_BYTES ? 1 : 0;
+    c.node_latency = o.node_form == 1 ? 1
+                     : o.node_form == 2 ? 0
+                     : (long long)n * m * (o.precision == MCF_FP32 ? 4 : 8) <= NODE_LATENCY_BYTES ? 1 : 0;
     c.nep = n;  // edge quantities are added per tail node
     c.nrp = (m + RES_EDGES - 1) / RES_EDGES;
     c.nnp = fused ? n : c.nblk_node;

@@ -47,7 +47,7 @@ class mcf_options(ctypes.Structure):
                 ("omega0", ctypes.c_double), ("device", ctypes.c_int32), ("kernel_mode", ctypes.c_int32),
                 ("stream", ctypes.c_void_p), ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t),
                 ("adapt_until", ctypes.c_int64), ("edge_waves", ctypes.c_int32), ("edge_vectors", ctypes.c_int32),
-                ("node_block", ctypes.c_int32), ("graphs", ctypes.c_int32)]
+                ("node_block", ctypes.c_int32), ("graphs", ctypes.c_int32), ("node_form", ctypes.c_int32)]
 
 
 class mcf_result(ctypes.Structure):

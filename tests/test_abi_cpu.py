@@ -109,6 +109,8 @@ def test_forced_launch_shapes_are_validated(mcf):
     _expect(mcf, E, opt=opt(edge_waves=4))                      # the pair is given together
     _expect(mcf, E, opt=opt(edge_vectors=2))
     _expect(mcf, E, opt=opt(node_block=128))
+    _expect(mcf, E, opt=opt(node_form=3))                       # 0 by size, 1 latency, 2 streaming
+    _expect(mcf, E, opt=opt(node_form=-1))
     _expect(mcf, E, opt=opt(precision=0, edge_waves=8, edge_vectors=3))   # compiled for FP32 only ...
     big = I.ring_instance(3000, 2, seed=1)                       # ... and columns of 64*1*2*2 < 3000
     with pytest.raises(mcf.MCFError) as ei:
