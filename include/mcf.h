@@ -90,8 +90,7 @@ typedef struct {
      * latency form while F is at most 512 MiB, else the streaming form); 1 = latency form (the
      * entry's own operands and a whole batch of in-edge loads in flight at once); 2 = streaming
      * form (fewer loads in flight per wave).  Other values: MCF_E_ARG.  The two forms compute the
-     * same quantities from the same source expressions and each is deterministic; iterates of the
-     * two have been seen to differ in the last bits. */
+     * same operations in the same order, so results are bitwise the same. */
     int32_t node_form;
 } mcf_options;
 

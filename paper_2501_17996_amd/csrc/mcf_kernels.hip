@@ -274,7 +274,7 @@ __device__ __forceinline__ double prox_alpha(double y, double beta, double w, do
         else hi = t;
         const double mid = 0.5 * (lo + hi);
         if (!(mid > lo && mid < hi)) break;  // the bracket is two adjacent doubles
-        double tn = t - h / (tq * ((p + 1.0) * t + p * y));
+        double tn = t - h / (tq * fma(p + 1.0, t, p * y));
         if (!(tn > lo && tn < hi)) tn = mid;
         if (tn == t) break;
         t = tn;
@@ -282,11 +282,14 @@ __device__ __forceinline__ double prox_alpha(double y, double beta, double w, do
     return -t;
 }
 
+// A sum of two products is written as one explicit fma: left to the compiler, which product
+// it fuses can depend on the code around the call, and so the rounding could differ between
+// kernels that share this code.
 template <int UTIL>
 __device__ __forceinline__ double prox_dual(double y, double beta, double w, double g, double c1, double tg)
 {
     if (UTIL == 0) {
-        const double s = sqrt(y * y + 4.0 * beta * w);
+        const double s = sqrt(fma(y, y, 4.0 * beta * w));
         return y <= 0.0 ? 0.5 * (y - s) : -2.0 * beta * w / (y + s);
     }
     if (UTIL == 2) return prox_alpha<UTIL>(y, beta, w, c1, tg);
@@ -295,7 +298,7 @@ __device__ __forceinline__ double prox_dual(double y, double beta, double w, dou
     const double k = half ? beta * w * w * 0.25 : c1 * beta * (1.0 / g - 1.0) * pow(w * g, 1.0 / (1.0 - g));
     auto hval = [&](double t, double &hp) {
         const double tp = half ? t : pow(t, c1);
-        hp = tp * ((c1 + 2.0) * t + (c1 + 1.0) * y);
+        hp = tp * fma(c1 + 2.0, t, (c1 + 1.0) * y);
         return tp * t * (t + y) - k;
     };
     const double hi = a + (half ? cbrt(k) : pow(k, 1.0 / (c1 + 2.0)));
@@ -894,9 +897,9 @@ __global__ __launch_bounds__(NB) void node_kernel(Consts c, Bufs<T> b, PartLayou
             y = (double)b.Y[x];
             w = (double)b.W[x];
         }
-        const double v = (2.0 / c.rho) * pn - ((2.0 - c.rho) / c.rho) * po;
+        const double v = fma(2.0 / c.rho, pn, -(((2.0 - c.rho) / c.rho) * po));
         const double yhat = (i != j) ? prox_dual<UTIL>(y - beta * v, beta, w, g, c.c1, -y) : 0.0;
-        const T yn = (T)(c.rho * yhat + (1.0 - c.rho) * y);
+        const T yn = (T)fma(c.rho, yhat, (1.0 - c.rho) * y);
         b.Y[x] = yn;
         if (PARTIAL) {
             const double d = (double)yn - y;
@@ -1191,7 +1194,7 @@ __device__ __forceinline__ void fused_body(const Consts &c, const Bufs<T> &b, co
         const long long x = (long long)j * ld + i;
         const double y = (double)yrow[r], w = (double)wrow[r];
         const double yhat = (i != j) ? prox_dual<UTIL>(y - beta * v, beta, w, g, c.c1, -y) : 0.0;
-        const T yn = (T)(rho * yhat + omr * y);
+        const T yn = (T)fma(rho, yhat, omr * y);
         Yn[x] = yn;
         if (PARTIAL) {
             const double d = (double)yn - y;

@@ -362,9 +362,9 @@ def test_graph_replays_equal_direct_launches(M, mode, precision):
 def test_node_forms_agree(M, precision):
     """The latency and streaming forms of the regular node launch, forced either way on one
     instance: each form is deterministic (two handles of one form stay bitwise equal), and the
-    two forms agree to the FP64 parity tolerance block after block, and their objectives after a
-    full solve to that tolerance (FP64) or to 1e-7 (FP32); iterates of the two forms have been
-    seen to differ in the last bits."""
+    two forms give bitwise the same iterates, scalars and objective, block after block and over
+    a full solve (the dual prox writes each sum of two products as one explicit fma, so the
+    compiler cannot round the two forms differently)."""
     inst = I.ring_instance(600, 6, seed=37)
     kw = dict(precision=precision, kernel_mode=M.MCF_KERNELS_TWO_PHASE, check_every=25, tol=1e-3)
     lat = gpu_solver(M, inst, node_form=1, **kw)
@@ -382,13 +382,12 @@ def test_node_forms_agree(M, precision):
             assert sa == sb
         F1, Y1, s1 = lat.get_state()
         F2, Y2, s2 = stm.get_state()
-        assert s1["k"] == s2["k"]
-        assert relerr(F1, F2) <= RTOL64 and relerr(Y1, Y2) <= RTOL64
-        assert s1["omega"] == pytest.approx(s2["omega"], rel=RTOL64)
+        np.testing.assert_array_equal(F1, F2)
+        np.testing.assert_array_equal(Y1, Y2)
+        assert s1 == s2
     a, b = lat.solve(), stm.solve()
     assert a["state_name"] == b["state_name"] == "converged"
-    # FP32 solves of the two forms have ended 3e-10 apart in the objective
-    assert a["primal_obj"] == pytest.approx(b["primal_obj"], rel=RTOL64 if precision == 0 else 1e-7)
+    assert a["iters"] == b["iters"] and a["primal_obj"] == b["primal_obj"]
 
 
 def test_graph_cache_past_its_bound(M):
