@@ -216,32 +216,37 @@ __device__ __forceinline__ double group_max(double x, double *lds)
 // w s^{1-g} / (1-g) (UTIL 2, g = alpha); u' for U' = u'(T); the traffic s(y) maximizing
 // y s + u(s), from u'(s) = -y, and the conjugate (-u)^*(y) = y s(y) + u(s(y)), both for y < 0.
 // For the alpha-fair utility w s^{1-g} = -y s at s = s(y), so the conjugate is (-y) s g/(1-g).
+// UTIL 3 is the power utility with g = 1/2 known when compiling: the same operations as UTIL 1
+// at g = 1/2, without the code of the general exponent (which sets the register count of the
+// node launch).
+constexpr int UTIL_POWER_HALF = 3;
 template <int UTIL>
 __device__ __forceinline__ double util_u(double s, double w, double g)
 {
     if (UTIL == 0) return w * log(s);
-    if (UTIL == 1) return w * pow(s, g);
+    if (UTIL == 1 || UTIL == UTIL_POWER_HALF) return w * pow(s, g);
     return w * pow(s, 1.0 - g) / (1.0 - g);
 }
 template <int UTIL>
 __device__ __forceinline__ double util_du(double s, double w, double g)
 {
     if (UTIL == 0) return w / s;
-    if (UTIL == 1) return w * g * pow(s, g - 1.0);
+    if (UTIL == 1 || UTIL == UTIL_POWER_HALF) return w * g * pow(s, g - 1.0);
     return w * pow(s, -g);
 }
 template <int UTIL>
 __device__ __forceinline__ double util_traffic(double y, double w, double g)
 {
     if (UTIL == 0) return w / (-y);
-    if (UTIL == 1) return pow(w * g / (-y), 1.0 / (1.0 - g));
+    if (UTIL == 1 || UTIL == UTIL_POWER_HALF) return pow(w * g / (-y), 1.0 / (1.0 - g));
     return pow(w / (-y), 1.0 / g);
 }
 template <int UTIL>
 __device__ __forceinline__ double util_conj(double y, double w, double g)
 {
     if (UTIL == 0) return -w + w * log(w) - w * log(-y);
-    if (UTIL == 1) return (1.0 / g - 1.0) * pow(w * g, 1.0 / (1.0 - g)) * pow(-y, -g / (1.0 - g));
+    if (UTIL == 1 || UTIL == UTIL_POWER_HALF)
+        return (1.0 / g - 1.0) * pow(w * g, 1.0 / (1.0 - g)) * pow(-y, -g / (1.0 - g));
     return (-y) * util_traffic<2>(y, w, g) * g / (1.0 - g);
 }
 
@@ -294,7 +299,7 @@ __device__ __forceinline__ double prox_dual(double y, double beta, double w, dou
     }
     if (UTIL == 2) return prox_alpha<UTIL>(y, beta, w, c1, tg);
     const double a = y < 0.0 ? -y : 0.0;
-    const bool half = c1 == 1.0;  // gamma = 1/2: t^3 + y t^2 - beta w^2 / 4
+    const bool half = UTIL == UTIL_POWER_HALF || c1 == 1.0;  // gamma = 1/2: t^3 + y t^2 - beta w^2 / 4
     const double k = half ? beta * w * w * 0.25 : c1 * beta * (1.0 / g - 1.0) * pow(w * g, 1.0 / (1.0 - g));
     auto hval = [&](double t, double &hp) {
         const double tp = half ? t : pow(t, c1);
@@ -1719,12 +1724,16 @@ template <typename T>
 hipError_t launch_node(const Consts &c, const Bufs<T> &b, const PartLayout &pl, bool check, bool partial,
                        hipStream_t st, hipEvent_t e0, hipEvent_t e1)
 {
+    // gamma = 1/2 (c1 = gamma / (1 - gamma) = 1) takes the kernels compiled for it
+    const bool half = c.utility == 1 && c.c1 == 1.0;
     if (c.node_block == 64) {
         if (c.utility == 0) node_go<T, 64, 0>(c, b, pl, check, partial, st, e0, e1);
+        else if (half) node_go<T, 64, UTIL_POWER_HALF>(c, b, pl, check, partial, st, e0, e1);
         else if (c.utility == 1) node_go<T, 64, 1>(c, b, pl, check, partial, st, e0, e1);
         else node_go<T, 64, 2>(c, b, pl, check, partial, st, e0, e1);
     } else {
         if (c.utility == 0) node_go<T, 256, 0>(c, b, pl, check, partial, st, e0, e1);
+        else if (half) node_go<T, 256, UTIL_POWER_HALF>(c, b, pl, check, partial, st, e0, e1);
         else if (c.utility == 1) node_go<T, 256, 1>(c, b, pl, check, partial, st, e0, e1);
         else node_go<T, 256, 2>(c, b, pl, check, partial, st, e0, e1);
     }
