@@ -577,3 +577,143 @@ def test_parallel_edges_equal_merged_capacity(orc):
         out.append((T, s.metrics()["primal_obj"]))
     np.testing.assert_allclose(out[0][0], out[1][0], rtol=1e-6, atol=1e-8)
     assert out[0][1] == pytest.approx(out[1][1], rel=1e-9)
+
+
+# ------------------------------------------- adaptive primal weight away from 1
+@pytest.mark.parametrize("theta,omega0", [(0.5, 1.0), (0.3, 1.0), (0.3, 3.0)])
+def test_primal_weight_update_away_from_one(orc, theta, omega0):
+    """(e-primal_weight) at iterations where omega^k != 1: omega^{k+1} =
+    (Delta_Y / Delta_F)^theta (omega^k)^(1 - theta), with the step norms
+    Delta_F = ||F^{k+1/2} - F^{k-1/2}||_F and Delta_Y = ||Y^{k+1} - Y^k||_F formed here
+    from the states read before and after the step (Section 2.4), and alpha = eta/omega,
+    beta = eta omega with eta = 1/sqrt(2 d_max) from the degrees (e-eta).  The runs pass
+    k = 100 and k = 200, so omega^k is the one an earlier adaptation left, away from 1 (and with
+    omega^0 = 3 also at k = 0): dropping the (omega^k)^(1 - theta) factor, or using the wrong
+    exponent, fails here."""
+    inst = I.config1(0)
+    n = inst.n
+    deg = np.bincount(inst.tail, minlength=n) + np.bincount(inst.head, minlength=n)
+    eta = 1.0 / math.sqrt(2.0 * deg.max())
+    s = orc.OracleSolver(inst, theta=theta, k_adapt=100, omega0=omega0)
+    checked = 0
+    for k in range(0, 201):
+        F0, Y0, sc0 = s.get_state()
+        assert sc0["k"] == k
+        s.step(check=False)
+        F1, Y1, sc1 = s.get_state()
+        dF = float(np.linalg.norm(F1 - F0))
+        dY = float(np.linalg.norm(Y1 - Y0))
+        if k % 100 == 0:
+            assert dF > 1e-5 and dY > 1e-5
+            want = (dY / dF) ** theta * sc0["omega"] ** (1.0 - theta)
+            assert sc1["omega"] == pytest.approx(want, rel=1e-12)
+            if k > 0 or omega0 != 1.0:
+                # the pin only bites where omega^k is away from 1 and the new value differs from
+                # both (dY/dF)^theta and the theta = 1/2 update by far more than the tolerance
+                assert abs(math.log(sc0["omega"])) > 0.01
+                assert abs(sc1["omega"] / (dY / dF) ** theta - 1.0) > 1e-3
+                if theta != 0.5:
+                    assert abs(sc1["omega"] / math.sqrt(dY / dF * sc0["omega"]) - 1.0) > 1e-3
+                checked += 1
+        else:
+            assert sc1["omega"] == sc0["omega"]
+        assert sc1["alpha"] == pytest.approx(eta / sc1["omega"], rel=1e-15)
+        assert sc1["beta"] == pytest.approx(eta * sc1["omega"], rel=1e-15)
+    assert checked == (3 if omega0 != 1.0 else 2)
+
+
+# --------------------------------------------- relative KKT from its three parts
+def _kkt_parts_by_definition(inst, Q, Fh, Y):
+    """p, d, rel_primal, rel_dual and rel_gap of a (Q, Fhat, Y) triple from dense algebra,
+    scalar minimizations and per-edge LPs: none of them from the oracle."""
+    n, m = inst.n, inst.m
+    A = R.incidence(n, inst.tail, inst.head)
+    W = R.weights_matrix(inst)
+    off = R.offdiag_mask(n)
+    T = -(Fh @ A.T)
+    assert (T[off] > 0).all()
+    Up = np.zeros((n, n))
+    Up[off] = R.dutil(inst, T[off], W[off])
+    G = Up @ A
+    D = Fh - Q
+    res = optimize.minimize_scalar(lambda g: np.sum((G - g * D) ** 2), bounds=(0, 1e4), method="bounded",
+                                   options={"xatol": 1e-13})
+    r = min(res.fun, np.sum(G * G))
+    reld = math.sqrt(max(r, 0.0) / np.sum(G * G))
+    p = -np.sum(R.util(inst, T[off], W[off]))
+    YA = Y @ A
+    d = -sum(_conj_numeric(inst, Y[i, j], W[i, j]) for i in range(n) for j in range(n) if i != j) \
+        - sum(_support_lp(YA[:, l], inst.cap[l]) for l in range(m))
+    Tdual = np.zeros((n, n))
+    for i in range(n):
+        for j in range(n):
+            if i != j:
+                Tdual[i, j] = optimize.minimize_scalar(
+                    lambda s_: -(Y[i, j] * s_ + R.util(inst, s_, W[i, j])), bounds=(1e-9, 1e4),
+                    method="bounded", options={"xatol": 1e-13}).x
+    relp = np.linalg.norm((Tdual - T)[off]) / np.linalg.norm(T[off])
+    relg = (p - d) / (1.0 + abs(p) + abs(d))
+    return {"p": p, "d": d, "rel_primal": relp, "rel_dual": reld, "rel_gap": relg, "Up": Up, "G": G}
+
+
+def test_relative_kkt_composition(orc):
+    """The relative KKT residual (the reading of the configurations' tolerances):
+    rel_gap = (p - d)/(1 + |p| + |d|) and rel_kkt = max(rel_primal, rel_dual, rel_gap), each
+    part computed here by definition.  Three triples make each part the strict maximum in
+    turn, so a rel_kkt that leaves a part out fails one of them; a fourth with one
+    off-diagonal Y_ij >= 0 (outside the conjugates' domain) must give rel_kkt = +inf."""
+    rng = np.random.default_rng(41)
+    n = 4
+    tail, head = zip(*[(j, i) for i in range(n) for j in range(n) if i != j])
+    tail, head = np.array(tail), np.array(head)
+    m = len(tail)
+    cap = rng.uniform(0.5, 2.0, m)
+    W = rng.uniform(0.5, 1.5, (n, n))
+    np.fill_diagonal(W, 0)
+    inst = _inst(n, tail, head, cap, W)
+    import oracle
+    s = orc.OracleSolver(inst)
+    # a feasible projected flow with T > 0 off the diagonal
+    Q0 = np.zeros((n, m))
+    Q0[head, np.arange(m)] = cap
+    Q0 += rng.normal(0, 0.2, (n, m))
+    Fh = np.stack([oracle.project(Q0[:, l], cap[l])[0] for l in range(m)], axis=1)
+    A = R.incidence(n, tail, head)
+    T = -(Fh @ A.T)
+    off = R.offdiag_mask(n)
+    Ystar = np.zeros((n, n))
+    Ystar[off] = -R.dutil(inst, T[off], W[off])        # prices that ask for exactly T: rel_primal = 0
+    base = _kkt_parts_by_definition(inst, Fh, Fh, Ystar)
+    G = base["G"]
+    cases = {
+        # D = 0: r = ||G||^2, rel_dual = 1 > rel_gap, rel_primal = 0
+        "rel_dual": (Fh, Ystar),
+        # prices a tenth of those asking for T: T(Y) = 10 T, rel_primal = 9
+        "rel_primal": (Q0, Ystar / 10.0),
+        # D parallel to G: r = 0, rel_dual = 0; rel_primal = 0; only the support gap is left
+        "rel_gap": (Fh - 0.05 * G, Ystar),
+    }
+    flat = lambda X: np.ascontiguousarray(X.T).reshape(-1)
+    for want, (Q, Y) in cases.items():
+        ref = _kkt_parts_by_definition(inst, Q, Fh, Y)
+        M = s.eval_residual(flat(Q), flat(Fh), flat(Y))
+        parts = {k: ref[k] for k in ("rel_primal", "rel_dual", "rel_gap")}
+        top = max(parts, key=parts.get)
+        assert top == want, (want, parts)
+        others = sorted(parts.values())
+        assert others[-1] > 1.5 * others[-2] + 1e-6, (want, parts)
+        assert M["primal_obj"] == pytest.approx(ref["p"], rel=1e-12)
+        assert M["dual_obj"] == pytest.approx(ref["d"], rel=1e-7)
+        assert M["rel_gap"] == pytest.approx(ref["rel_gap"], rel=1e-6, abs=1e-9)
+        assert M["rel_primal"] == pytest.approx(ref["rel_primal"], rel=1e-5, abs=1e-7)
+        assert M["rel_dual"] == pytest.approx(ref["rel_dual"], rel=1e-5, abs=1e-6)
+        assert M["rel_kkt"] == pytest.approx(max(parts.values()), rel=1e-5, abs=1e-6)
+    # one off-diagonal price >= 0: the dual function is -inf, the gap and rel_kkt +inf,
+    # while T stays feasible (r finite)
+    for bad in (0.0, 0.25):
+        Y = Ystar.copy()
+        Y[2, 1] = bad
+        M = s.eval_residual(flat(Q0), flat(Fh), flat(Y))
+        assert math.isfinite(M["r"]) and M["infeasible_frac"] == 0.0
+        assert M["dual_obj"] == -math.inf
+        assert math.isinf(M["rel_gap"]) and math.isinf(M["rel_kkt"])
