@@ -1,16 +1,19 @@
 """Benchmark of the PDMCF hot path on one MI355X.
 
-A step is one full solve from the cold start to the stopping tolerance: every
-PDHG iteration (edge phase, node phase, FP64 control) plus the residual/KKT
-check every `check_every` iterations, with the instance already resident in
-HBM.  Default workload: n = 200 ring + chords with out-degree 10 (m = 2000),
-capacities U[0.5, 2], log utility with w ~ U[0.5, 1.5], FP32 iterates with FP64
-reductions, relative KKT tolerance 1e-4.
+Default workload: config4, the largest single-GPU configuration: n = 10000 nodes, ring +
+chords with out-degree 10 (m = 100000), capacities U[0.5, 2], log utility with
+w ~ U[0.5, 1.5], FP32 iterates (1e9 flow variables, 4 GB per iterate array) with FP64
+reductions, relative KKT tolerance 1e-3, instance resident in HBM.  A step is one block of 50
+whole PDHG iterations of the running solve (edge phase, node phase and FP64 control in every
+iteration; the residual/KKT check, its residual pass and the stop test at the block's last
+iteration), replayed from the block's captured HIP graph.  The same run also reports the
+time to the tolerance of a full config4 solve from the cold start, the full solves of config2
+and config3, a short serving stream (p50/p99) and the saturated batching pool.
 
 Prints one JSON line with the throughput in edge-dest updates per second
-(n * m * iterations / second), the roofline of the dominant (edge-phase) kernel
-measured with HIP events inside the timed region, and the CPU oracle timed on
-a bounded sample of the same workload.
+(n * m * iterations / second), the roofline of the iteration measured with HIP events on the
+solver's stream inside the timed region, and the CPU oracle timed on a bounded sample of the
+same workload.
 """
 import argparse
 import json
@@ -41,7 +44,7 @@ def kernels_sha256() -> str:
     """Hash of the kernel source and the launch-shape table the traffic figures belong to."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("mcf_kernels.hip", "tuned_shapes.inc"):
+    for f in ("mcf_kernels.hip", "tuned_shapes.inc", "tuned_pool.inc"):
         h.update(open(os.path.join(ROOT, "paper_2501_17996_amd", "csrc", f), "rb").read())
     return h.hexdigest()
 
@@ -75,36 +78,17 @@ def alg_bytes(n: int, m: int, s: int, fused: bool, check: bool) -> float:
     return b
 
 
-def large_instance(mcf, torch):
-    """The HBM-bound size beside the headline one: config4 (n = 1e4, m = 1e5, 1e9 FP32 variables).
-    Ten warm-up iterations from the cold start, then 41 with the dispatch-recorded events on; the
-    sampled iterations (k = 14, 21, ..., 49) are all regular ones (no check, no adaptation)."""
-    inst, _, desc = workload("c4")
-    # launched one by one: the events recorded by the dispatches then sample single iterations
-    S = mcf.Solver(inst, precision=mcf.MCF_FP32, tol=1e-3, check_every=1000, max_iter=200000,
-                   stream=torch.cuda.current_stream().cuda_stream, graphs=0)
+def cpu_model() -> str:
     try:
-        S.run(10)
-        torch.cuda.synchronize()
-        mcf.mcf_enable_kernel_timing(S.h, True)
-        S.run(41)
-        torch.cuda.synchronize()
-        ms, cnt = mcf.mcf_kernel_time(S.h)
-        mcf.mcf_enable_kernel_timing(S.h, False)
-    finally:
-        S.close()
-    n, m = inst.n, inst.m
-    t = ms * 1e-3 / max(1, cnt)
-    alg = alg_bytes(n, m, 4, False, False)
-    return {"workload": desc.split(", solve")[0] + "; FP32; regular iterations after 10 from the cold start",
-            "n": n, "m": m, "bound": "hbm", "achieved": alg / t / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": alg / t / 1e9 / HBM_PEAK_GBS, "traffic": measured_traffic("c4"),
-            "alg_bytes_per_iteration": alg, "kernel": "edge + node phases (one iteration)",
-            "ms_per_iteration": t * 1e3, "iterations_timed": cnt,
-            "edge_dest_updates_per_s": n * m / t}
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
-def cpu_baseline(inst, tol, check_every, budget_s: float):
+def cpu_baseline_solve(inst, tol, check_every, budget_s: float):
     """The FP64 oracle on the host cores, on the same instance from the cold start, in blocks of
     check_every iterations (the last one checked) until the relative KKT residual reaches tol or
     the time budget runs out.  When it converges, its primal objective is the FP64 reference the
@@ -127,11 +111,100 @@ def cpu_baseline(inst, tol, check_every, budget_s: float):
             f"{iters} PDHG iterations of the same instance from the cold start (residual every {check_every}), "
             f"FP64, stopped at the time budget before reaching rel KKT {tol:g}")
     return {"value": inst.n * inst.m * iters / dt, "unit": "edge-dest updates/s", "cores": threads,
-            "kind": "oracle", "sample": f"{what}, {dt:.1f} s on {threads} threads",
+            "kind": "oracle", "sample": f"{what}, {dt:.1f} s on {threads} threads of {cpu_model()}",
             "converged": converged, "iters": iters, "primal_obj": mo["primal_obj"] if converged else None}
 
 
+def cpu_baseline_iterations(inst, iters: int, threads: int):
+    """The FP64 oracle's per-iteration time on the host: `iters` iterations from the cold start
+    (the first also touches the oracle's arrays for the first time), each timed; the median."""
+    import oracle
+    O = oracle.OracleSolver(inst, threads=threads)
+    times = []
+    for _ in range(iters):
+        t0 = time.perf_counter()
+        O.step(check=False)
+        times.append(time.perf_counter() - t0)
+    O.close()
+    times.sort()
+    return times[len(times) // 2], times
+
+
+def timed_solves(mcf, torch, name, reps, check_every):
+    """`reps` full solves of a configuration from the cold start (setup and upload done once):
+    wall time to the tolerance, iterations, throughput."""
+    inst, tol, desc = workload(name)
+    S = mcf.Solver(inst, precision=mcf.MCF_FP32, tol=tol, check_every=check_every, max_iter=200000,
+                   stream=torch.cuda.current_stream().cuda_stream)
+    try:
+        S.solve()          # warm-up: captures the block graphs
+        S.reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        iters = 0
+        for _ in range(reps):
+            S.reset()
+            st = S.solve()
+            iters += st["iters"]
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+    finally:
+        S.close()
+    return {"workload": desc + f", FP32 iterates, residual every {check_every}", "time_to_tol_ms": dt * 1e3,
+            "iters": iters // reps, "state": st["state_name"], "rel_kkt": st["rel_kkt"],
+            "primal_obj": st["primal_obj"], "edge_dest_updates_per_s": inst.n * inst.m * (iters / reps) / dt}
+
+
+def pool_leg(mcf, torch, slots: int, steps: int, K: int):
+    """The batching pool saturated: the first `slots` requests of the serving stream (seed 1000+r,
+    n ~ U{20..500}, out-degree ~ U{4..16}, log/power(0.5)) admitted together, FP32, run for
+    `steps` steps of K iterations (tolerance out of reach, so every slot iterates throughout).
+    The timed unit is one pool iteration over every slot (the persistent iteration launch, plus
+    the amortised check, residual, control and gather), timed with events on the pool's stream."""
+    from paper_2501_17996_amd import instances as I
+    stream = torch.cuda.Stream()     # a stream of its own (default priority): the events bracket its work
+    insts = [I.serving_request(r) for r in range(slots)]
+    pool = mcf.Pool(mcf.MCF_FP32, 0, slots, K, stream=stream.cuda_stream)
+    hs = [mcf.Solver(i, precision=mcf.MCF_FP32, tol=1e-14, check_every=K, max_iter=10 ** 8) for i in insts]
+    for h in hs:
+        pool.admit(h)
+    for _ in range(3):
+        pool.step(K)
+        pool.sync()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(steps):
+        pool.step(K)
+    e1.record(stream)
+    pool.sync()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev_ms = e0.elapsed_time(e1)
+    shape = pool.shape()
+    pool.close()
+    for h in hs:
+        h.close()
+    per_it = ev_ms * 1e-3 / (steps * K)
+    alg = sum(alg_bytes(i.n, i.m, 4, True, False) * (K - 1) / K + alg_bytes(i.n, i.m, 4, True, True) / K
+              for i in insts)
+    upd = sum(i.n * i.m for i in insts)
+    return {"workload": f"{slots} requests of the serving stream in one pool, FP32, steps of {K} iterations",
+            "n_total": sum(i.n for i in insts), "nm_total": upd, "shape": shape,
+            "us_per_iteration": per_it * 1e6, "edge_dest_updates_per_s": upd / per_it,
+            "wall_updates_per_s": upd * steps * K / wall,
+            "roofline": {"bound": "hbm", "achieved": alg / per_it / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": alg / per_it / 1e9 / HBM_PEAK_GBS, "traffic": measured_traffic("pool"),
+                         "alg_bytes_per_iteration": alg,
+                         "working_set_bytes": sum(mcf.mcf_workspace_bytes(i.n, i.m, 1) for i in insts)}}
+
+
 def serve_bench(args):
+    print(json.dumps(serve_run(args)), flush=True)
+
+
+def serve_run(args):
     """Serving stream: requests r = 0.. (seed 1000+r; n ~ U{20..500}, out-degree ~ U{4..16},
     log or power(0.5) utility), FP32 iterates batched in one pool, Poisson arrivals at
     `load` x the throughput of a saturated calibration run.  Reports p50/p99 latency and
@@ -178,11 +251,11 @@ def serve_bench(args):
         "latency_p50_s": summ["latency_p50_s"], "latency_p99_s": summ["latency_p99_s"],
         "service_p50_s": summ["service_p50_s"], "service_p99_s": summ["service_p99_s"],
         "edge_dest_updates_per_s": summ["edge_dest_updates_per_s"], "converged": summ["converged"],
-        "requests": summ["requests"], "makespan_s": summ["makespan_s"],
+        "requests": summ["requests"], "rejected": summ["rejected"], "makespan_s": summ["makespan_s"],
         "single_fp64": {"requests": n_single, "instances_per_s": n_single / t_single,
                         "edge_dest_updates_per_s": upd / t_single},
     }
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def warmstart_bench(args):
@@ -293,27 +366,32 @@ def knn_bench(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c4",
+                    help="c4 (default; steps are blocks of iterations of one solve), c2 or c3 (steps are full "
+                         "solves), pool, serve, warmstart, knn")
+    ap.add_argument("--block", type=int, default=50, help="c4: iterations per step (the last one checked)")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--check-every", type=int, default=None,
                     help="residual check interval: default 50 for single solves (a check costs about two "
-                         "iterations; a solve overshoots by fewer than K), 20 for the serving loop")
+                         "iterations; a solve overshoots by fewer than K), 20 for the serving loop and the pool")
     ap.add_argument("--cpu-budget", type=float, default=30.0,
-                    help="seconds of host time for the oracle leg (it stops earlier once converged)")
+                    help="seconds of host time for the oracle's solve legs (they stop earlier once converged)")
+    ap.add_argument("--cpu-iters", type=int, default=3, help="c4: oracle iterations timed for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-full-solve", action="store_true", help="c4: skip the time-to-tolerance solve")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="c4: skip the config2/config3 solves, the pool and the serving legs")
     ap.add_argument("--kernel-mode", type=int, default=0, help="0 auto, 1 two-phase, 2 fused")
-    ap.add_argument("--no-large", action="store_true",
-                    help="skip the config4 roofline leg of the default run")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 256 MiB device copy first (a counter reference of known size)")
     ap.add_argument("--iters", type=int, default=0,
-                    help="run this many iterations per step instead of a full solve (large workloads)")
+                    help="c2/c3: run this many iterations per step instead of a full solve")
     ap.add_argument("--requests", type=int, default=2000, help="serving workload: stream length")
     ap.add_argument("--calib", type=int, default=200, help="serving workload: saturated calibration requests")
     ap.add_argument("--load", type=float, default=0.8, help="serving workload: arrival rate / saturated rate")
-    ap.add_argument("--slots", type=int, default=64, help="serving workload: pool slots")
+    ap.add_argument("--slots", type=int, default=64, help="serving workload and pool: pool slots")
     ap.add_argument("--single", type=int, default=50, help="serving workload: FP64 single-instance comparison size")
     ap.add_argument("--serve-budget-gb", type=float, default=16.0)
     ap.add_argument("--serve-max-iter", type=int, default=60000)
@@ -324,7 +402,8 @@ def main():
                          "workloads, 1000 for the serving stream")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "this build runs on one GPU (the single-instance path and the pool); "
+                                   "--gpus must be 1"}))
         raise SystemExit(2)
 
     if args.workload == "warmstart":
@@ -334,7 +413,7 @@ def main():
         knn_bench(args)
         return
     if args.check_every is None:
-        args.check_every = 20 if args.workload == "serve" else 50
+        args.check_every = 20 if args.workload in ("serve", "pool") else 50
     if args.workload == "serve":
         if args.adapt_until is None:
             args.adapt_until = 1000
@@ -347,11 +426,16 @@ def main():
     from paper_2501_17996_amd import mcf
 
     torch.cuda.set_device(0)
+    if args.workload == "pool":
+        print(json.dumps(pool_leg(mcf, torch, args.slots, args.steps, args.check_every)), flush=True)
+        return
     inst, tol, desc = workload(args.workload)
     prec = mcf.MCF_FP32 if args.precision == "fp32" else mcf.MCF_FP64
     s = 4 if prec == mcf.MCF_FP32 else 8
     stream = torch.cuda.current_stream()
-    S = mcf.Solver(inst, precision=prec, tol=tol, check_every=args.check_every, max_iter=200000,
+    blocks = args.workload == "c4"
+    K = args.block if blocks else args.check_every
+    S = mcf.Solver(inst, precision=prec, tol=tol, check_every=K, max_iter=200000,
                    stream=stream.cuda_stream, kernel_mode=args.kernel_mode, adapt_until=args.adapt_until)
     if args.copy_calibration:
         src = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda").fill_(1.0)
@@ -361,6 +445,8 @@ def main():
         del src, dst
 
     def step():
+        if blocks:
+            return S.run(K)          # K more iterations of the running solve, the last one checked
         S.reset()
         return S.run(args.iters) if args.iters > 0 else S.solve()
 
@@ -373,15 +459,15 @@ def main():
     t0 = time.perf_counter()
     for _ in range(args.steps):
         st = step()
-        iters += st["iters"]
+        iters += K if blocks else st["iters"]
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     edge_ms, launches = mcf.mcf_kernel_time(S.h)
     mcf.mcf_enable_kernel_timing(S.h, False)
     n, m = inst.n, inst.m
     fused = S.layout()["kernel_mode"] == "fused"
-    # the sampled launches keep the check / regular mix of the whole run
-    checks = launches / args.check_every
+    # the timed iterations keep the check / regular mix of the whole run
+    checks = launches / K
     alg = alg_bytes(n, m, s, fused, False) * (launches - checks) + alg_bytes(n, m, s, fused, True) * checks
     achieved = alg / (edge_ms * 1e-3) / 1e9 if edge_ms > 0 else 0.0
     value = n * m * iters / dt
@@ -399,10 +485,12 @@ def main():
         "dtype": "f32" if prec == mcf.MCF_FP32 else "f64",
         "data": "synthetic",
         "config": {"workload": desc, "n": n, "m": m, "precision": args.precision, "adapt_until": args.adapt_until,
-                   "reductions": "f64", "check_every": args.check_every, "tol": tol,
-                   "iters_per_step": iters / args.steps, "final_rel_kkt": st["rel_kkt"],
-                   "step": f"{args.iters} iterations from the cold start" if args.iters > 0 else "full solve",
-                   "time_to_tol_ms": dt / args.steps * 1e3},
+                   "reductions": "f64", "check_every": K, "tol": tol,
+                   "step": (f"{K} iterations of one solve (the last checked), replayed from the block's graph"
+                            if blocks else f"{args.iters} iterations from the cold start" if args.iters > 0
+                            else "full solve from the cold start"),
+                   "iters_per_step": iters / args.steps, "k_after_timing": st["iters"],
+                   "rel_kkt_after_timing": st["rel_kkt"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(args.workload) if args.kernel_mode == 0 else None,
@@ -410,22 +498,66 @@ def main():
                      "kernel": "fused iteration" if fused else "edge + node phases (one iteration)",
                      "avg_launch_us": edge_ms * 1e3 / max(1, launches),
                      "launches": launches,
-                     "events": "on the solver's stream around each timed step (every launch of its iterations, "
-                               "checks and control included; blocks replayed from captured graphs)"},
+                     "events": "one pair of HIP events on the solver's stream around each timed step: every "
+                               "launch of its iterations, the check, residual pass and control included"},
     }
-    if args.workload == "c2" and args.iters == 0 and not args.no_large:
-        S.close()
-        try:
-            out["large_instance"] = large_instance(mcf, torch)
-        except Exception as e:  # the headline line must still print
-            out["large_instance"] = {"error": f"{type(e).__name__}: {e}"}
+    if not blocks:
+        out["config"]["time_to_tol_ms"] = dt / args.steps * 1e3
+        out["config"]["final_rel_kkt"] = st["rel_kkt"]
+    if blocks and not args.no_full_solve:
+        # time to the tolerance: one full solve from the cold start, instance resident in HBM
+        print(f"[bench] full solve of {args.workload} to rel KKT {tol:g}", file=sys.stderr, flush=True)
+        S.reset()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        fs = S.solve()
+        torch.cuda.synchronize()
+        t_solve = time.perf_counter() - t1
+        out["time_to_tol"] = {"seconds": t_solve, "iters": fs["iters"], "state": fs["state_name"],
+                              "rel_kkt": fs["rel_kkt"], "primal_obj": fs["primal_obj"], "tol": tol,
+                              "check_every": K, "edge_dest_updates_per_s": n * m * fs["iters"] / t_solve}
+    S.close()
+    p_c2 = None
+    if blocks and not args.no_extras:
+        print("[bench] config2 / config3 solves, pool, serving", file=sys.stderr, flush=True)
+        extras = {"c2": timed_solves(mcf, torch, "c2", 5, 50), "c3": timed_solves(mcf, torch, "c3", 3, 50)}
+        gold = os.path.join(ROOT, "tests", "golden", "oracle_c3_golden.json")
+        if os.path.exists(gold):
+            p_ref = json.load(open(gold))["solve"]["primal_obj"]
+            extras["c3"]["fp64_oracle_objective"] = p_ref
+            extras["c3"]["fp64_oracle_objective_relerr"] = (abs(extras["c3"]["primal_obj"] - p_ref)
+                                                             / max(1.0, abs(p_ref)))
+        extras["pool"] = pool_leg(mcf, torch, args.slots, 20, 20)
+        sargs = argparse.Namespace(**vars(args))
+        sargs.requests, sargs.calib, sargs.single, sargs.check_every = 300, 64, 20, 20
+        sargs.adapt_until = 1000
+        extras["serving"] = serve_run(sargs)
+        out["extras"] = extras
     if not args.no_cpu_baseline:
-        cb = cpu_baseline(inst, tol, args.check_every, args.cpu_budget)
-        p_ref = cb.pop("primal_obj")
-        out["cpu_baseline"] = cb
-        if p_ref is not None and args.iters == 0:
-            # the GPU result against the FP64 oracle at the same KKT tolerance
-            out["fp64_oracle_objective_relerr"] = abs(st["primal_obj"] - p_ref) / max(1.0, abs(p_ref))
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        if blocks:
+            threads = max(1, min(16, os.cpu_count() or 1))
+            med, times = cpu_baseline_iterations(inst, args.cpu_iters, threads)
+            out["cpu_baseline"] = {
+                "value": n * m / med, "unit": "edge-dest updates/s", "cores": threads, "kind": "oracle",
+                "sample": f"median of {args.cpu_iters} FP64 PDHG iterations of the same instance from the cold "
+                          f"start (edge and node phases, no check) on {threads} threads of {cpu_model()}: "
+                          + ", ".join(f"{t:.2f}" for t in times) + " s",
+                "s_per_iteration": med}
+            if "extras" in out:
+                cb = cpu_baseline_solve(workload("c2")[0], 1e-4, 50, args.cpu_budget)
+                p_c2 = cb.pop("primal_obj")
+                out["extras"]["c2"]["cpu_baseline"] = cb
+        else:
+            cb = cpu_baseline_solve(inst, tol, args.check_every, args.cpu_budget)
+            p_c2 = cb.pop("primal_obj")
+            out["cpu_baseline"] = cb
+        if p_c2 is not None:
+            tgt = out["extras"]["c2"] if blocks else out
+            gpu_p = tgt["primal_obj"] if blocks else st["primal_obj"]
+            if blocks or args.iters == 0:
+                # the GPU result against the FP64 oracle at the same KKT tolerance
+                tgt["fp64_oracle_objective_relerr"] = abs(gpu_p - p_c2) / max(1.0, abs(p_c2))
     print(json.dumps(out), flush=True)
 
 

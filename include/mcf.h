@@ -83,8 +83,8 @@ typedef struct {
     int32_t edge_waves, edge_vectors, node_block;
     /* 1 (default): each block of check_every iterations is captured once per block shape into a
      * HIP graph and replayed, which shortens the gap between dependent launches; 0: launched one
-     * by one.  Results are the same either way.  Kernel timing (mcf_enable_kernel_timing) always
-     * launches directly. */
+     * by one.  Results are the same either way.  With kernel timing on (mcf_enable_kernel_timing),
+     * blocks are still replayed from their graphs and one pair of events spans each solve or run. */
     int32_t graphs;
     /* Form of the regular two-phase node launch: 0 (default) = chosen from the size of F (the
      * latency form while F is at most 512 MiB, else the streaming form); 1 = latency form (the
@@ -214,23 +214,48 @@ int mcf_layout(const mcf_solver *s, int32_t *ld, int32_t *edge_block, int32_t *e
  * instance is evaluated at the last iteration of each mcf_pool_step.  Instances are admitted
  * and retired between steps (continuous batching); a converged instance stops iterating at
  * once and its slot can be reused after mcf_pool_retire.
+ * The pool's iteration counter and work-list sizes live in device memory, and the launch grids
+ * are the work counts rounded up (at most 1/8 idle), so a step is replayed from a captured HIP
+ * graph whichever instances are admitted; a graph is captured per step length, set of
+ * iterations at which some instance adapts omega, and grid.
  * Usage: create solvers (optionally inside caller workspaces), admit them, then repeat
  * { mcf_pool_step; host work; mcf_pool_sync; poll; retire; admit }.  While admitted, a solver
  * answers only mcf_status (the record of the last sync); its other calls return MCF_E_STATE. */
 typedef struct mcf_pool mcf_pool;
 enum { MCF_POOL_MAX_SLOTS = 256 };
 
-/* Creates a pool on `device`.  precision: MCF_FP32 or MCF_FP64 for every instance admitted;
- * hbm_budget: largest sum of mcf_workspace_bytes of the admitted instances (0: no limit);
- * max_slots: 1 .. MCF_POOL_MAX_SLOTS; check_every: default step length for callers;
- * stream: hipStream_t or NULL for a stream owned by the pool. */
-int mcf_pool_create(int32_t device, int32_t precision, size_t hbm_budget, int32_t max_slots, int32_t check_every,
-                    void *stream, mcf_pool **out);
+typedef struct {
+    int32_t device;         /* HIP device ordinal */
+    int32_t precision;      /* MCF_FP32 or MCF_FP64: the precision of every instance admitted */
+    size_t hbm_budget;      /* largest sum of mcf_workspace_bytes of the admitted instances (0: no limit) */
+    int32_t max_slots;      /* 1 .. MCF_POOL_MAX_SLOTS */
+    int32_t check_every;    /* default step length for callers */
+    int32_t n_max;          /* largest n admitted, 2 .. 512 (0: 512); it sets the launch shape */
+    /* Waves per node workgroup: 8 or (FP32 only) 4; 0 = the measured choice for n_max and the
+     * precision (the table tune.py writes).  Results depend on it only through the order of
+     * floating-point sums, and never on which other instances share the pool. */
+    int32_t waves;
+    int32_t graphs;         /* 1 (default): steps replayed from captured graphs; 0: launched one by one */
+    void *stream;           /* hipStream_t or NULL for a stream owned by the pool */
+} mcf_pool_options;
+
+/* Fills *o with the defaults: FP32, no budget, 64 slots, check_every 20, n_max 512, measured
+ * shape, graphs on, device 0, own stream. */
+void mcf_pool_options_default(mcf_pool_options *o);
+
+/* Creates a pool (opt NULL: the defaults).  MCF_E_ARG for an invalid option. */
+int mcf_pool_create(const mcf_pool_options *opt, mcf_pool **out);
+
+/* The launch shape in use: waves per node workgroup, the grid of the iteration launch for the
+ * instances now admitted, and the largest entries per lane (ceil(n_max / 64) rounded up to 1,
+ * 2, 4 or 8). */
+int mcf_pool_shape(const mcf_pool *p, int32_t *waves, int32_t *grid, int32_t *max_ept);
 
 /* Admits a solver into a free slot.  MCF_E_NOMEM when no slot is free or the budget would be
  * exceeded (retry after a retire); MCF_E_ARG when the solver is already pooled, has another
- * precision, or uses the two-phase iteration (n > 512); MCF_E_STATE when it has converged or
- * diverged.  The solver keeps its state and continues from its current iteration. */
+ * precision, uses the two-phase iteration or has more than n_max nodes; MCF_E_STATE when it
+ * has converged or diverged.  The solver keeps its state and continues from its current
+ * iteration. */
 int mcf_pool_admit(mcf_pool *p, mcf_solver *s, int32_t *slot);
 
 /* Enqueues `iters` pool iterations (the last one checks every instance) and returns without

@@ -7,6 +7,7 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libmcf.so")
 SOURCES = [os.path.join(HERE, "csrc", f) for f in ("mcf_kernels.hip", "mcf_runtime.hip")]
 HEADERS = [os.path.join(HERE, "csrc", "mcf_internal.h"), os.path.join(HERE, "csrc", "tuned_shapes.inc"),
+           os.path.join(HERE, "csrc", "tuned_pool.inc"),
            os.path.join(ROOT, "include", "mcf.h")]
 
 HIPCC_FLAGS = [

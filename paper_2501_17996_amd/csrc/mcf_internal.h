@@ -151,12 +151,32 @@ struct SlotDesc {
     int par0, active;
 };
 
-constexpr int POOL_WAVES = 8;  // waves per node workgroup in the batched iteration
+// Device-resident state of a pool: its iteration counter and the sizes of its work lists.  The
+// kernels of a step read G (iteration `it` of the step is G + it) and the list sizes from here,
+// so a step's launches carry no value that changes between steps and can be replayed from a
+// captured graph; the last launch of each step advances G.
+struct PoolState {
+    long long G;
+    int nwork;  // node items (slot, node) of the batched iteration
+    int nres;   // residual items (slot, block of RES_EDGES edges)
+};
+
+// Launch shape of a pool: waves per node workgroup (4 or 8), the grids of the iteration and
+// residual launches (the item counts rounded up; set per step), and the largest entries per lane
+// of an admitted instance (1, 2, 4 or 8: n <= 64 ept).
+struct PoolShape {
+    int waves, grid, res_grid, max_ept;
+};
 
 template <typename T>
-hipError_t launch_pool_iteration(const SlotDesc<T> *slots, const int2 *work, int nwork, int nslots, int max_m,
-                                 int max_ept, long long G, bool check, bool control, hipStream_t st);
+hipError_t launch_pool_iteration(const SlotDesc<T> *slots, const int2 *work, const int *res_off, const PoolState *ps,
+                                 int nslots, PoolShape sh, int it, bool check, bool control, hipStream_t st);
 template <typename T>
-hipError_t launch_pool_gather(const SlotDesc<T> *slots, int nslots, DevScalars *out, hipStream_t st);
+hipError_t launch_pool_gather(const SlotDesc<T> *slots, int nslots, DevScalars *out, PoolState *ps, int iters,
+                              hipStream_t st);
+// the pool shapes compiled into the library, and the measured choice for a pool of iterate
+// size `bytes` whose instances have at most n_max nodes
+bool pool_waves_valid(int waves, int bytes);
+PoolShape pool_shape_for(int n_max, int bytes);
 
 }  // namespace mcf

@@ -1479,33 +1479,40 @@ __device__ __forceinline__ bool slot_live(const SlotDesc<T> &d, long long G, lon
 
 // CHECK is uniform over a launch (every slot checks at the same pool iteration), so the
 // check variant is a kernel of its own and the register count of the regular kernel stays low.
-template <typename T, int EPT, int UTIL, bool CHECK>
+template <typename T, int EPT, int UTIL, bool CHECK, int NWV>
 __device__ __forceinline__ void pool_body(const SlotDesc<T> &d, int parity, int j, bool partial, double *vsh,
                                           double *red, int2 *incs)
 {
     // the slot's stop flag was read by slot_live
-    if (CHECK) fused_body<T, EPT, UTIL, true, true, POOL_WAVES, false>(d.c, d.b, d.pl, parity, j, vsh, red, incs);
+    if (CHECK) fused_body<T, EPT, UTIL, true, true, NWV, false>(d.c, d.b, d.pl, parity, j, vsh, red, incs);
     else if (partial)
-        fused_body<T, EPT, UTIL, false, true, POOL_WAVES, false>(d.c, d.b, d.pl, parity, j, vsh, red, incs);
-    else fused_body<T, EPT, UTIL, false, false, POOL_WAVES, false>(d.c, d.b, d.pl, parity, j, vsh, red, incs);
+        fused_body<T, EPT, UTIL, false, true, NWV, false>(d.c, d.b, d.pl, parity, j, vsh, red, incs);
+    else fused_body<T, EPT, UTIL, false, false, NWV, false>(d.c, d.b, d.pl, parity, j, vsh, red, incs);
 }
 
-template <typename T, int EPT, bool CHECK>
+template <typename T, int EPT, bool CHECK, int NWV>
 __device__ __forceinline__ void pool_util(const SlotDesc<T> &d, int parity, int j, bool partial, double *vsh,
                                           double *red, int2 *incs)
 {
-    if (d.c.utility == 0) pool_body<T, EPT, 0, CHECK>(d, parity, j, partial, vsh, red, incs);
-    else if (d.c.utility == 1) pool_body<T, EPT, 1, CHECK>(d, parity, j, partial, vsh, red, incs);
-    else pool_body<T, EPT, 2, CHECK>(d, parity, j, partial, vsh, red, incs);
+    if (d.c.utility == 0) pool_body<T, EPT, 0, CHECK, NWV>(d, parity, j, partial, vsh, red, incs);
+    else if (d.c.utility == 1) pool_body<T, EPT, 1, CHECK, NWV>(d, parity, j, partial, vsh, red, incs);
+    else pool_body<T, EPT, 2, CHECK, NWV>(d, parity, j, partial, vsh, red, incs);
 }
 
-template <typename T, bool CHECK>
-__global__ __launch_bounds__(64 * POOL_WAVES) void pool_fused_kernel(const SlotDesc<T> *slots, const int2 *work,
-                                                                     long long G)
+// Iteration G + it of the pool: workgroup b runs the fused body of work item b = (slot, node j)
+// with NWV waves.  The grid is the item count rounded up (so that a captured step fits every
+// count up to its grid); workgroups past the count read from the pool state return at once.
+// The dynamic LDS holds the V (and T) sums of NWV waves at the largest entries per lane the
+// pool admits.
+template <typename T, int NWV, bool CHECK>
+__global__ __launch_bounds__(64 * NWV) void pool_fused_kernel(const SlotDesc<T> *slots, const int2 *work,
+                                                              const PoolState *ps, int it)
 {
     extern __shared__ double vsh[];
-    __shared__ double red[2 * POOL_WAVES];
+    __shared__ double red[2 * NWV];
     __shared__ int2 incs[FUSED_INC_CHUNK];
+    if ((int)blockIdx.x >= ps->nwork) return;
+    const long long G = ps->G + it;
     const int2 wk = work[blockIdx.x];
     const SlotDesc<T> &d = slots[wk.x];
     long long k;
@@ -1513,43 +1520,56 @@ __global__ __launch_bounds__(64 * POOL_WAVES) void pool_fused_kernel(const SlotD
     const int parity = d.par0 ^ (int)((G - d.G0) & 1);
     const bool partial = CHECK || adapts_at(d.c, k);
     const int n = d.c.n;
-    if (n <= 64) pool_util<T, 1, CHECK>(d, parity, wk.y, partial, vsh, red, incs);
-    else if (n <= 128) pool_util<T, 2, CHECK>(d, parity, wk.y, partial, vsh, red, incs);
-    else if (n <= 256) pool_util<T, 4, CHECK>(d, parity, wk.y, partial, vsh, red, incs);
-    else pool_util<T, 8, CHECK>(d, parity, wk.y, partial, vsh, red, incs);
+    if (n <= 64) pool_util<T, 1, CHECK, NWV>(d, parity, wk.y, partial, vsh, red, incs);
+    else if (n <= 128) pool_util<T, 2, CHECK, NWV>(d, parity, wk.y, partial, vsh, red, incs);
+    else if (n <= 256) pool_util<T, 4, CHECK, NWV>(d, parity, wk.y, partial, vsh, red, incs);
+    else pool_util<T, 8, CHECK, NWV>(d, parity, wk.y, partial, vsh, red, incs);
 }
 
-// grid (max over slots of the residual blocks, slots)
+// Residual pass of every slot: workgroup b is block b - res_off[s] of slot s, where res_off
+// (nslots + 1 entries, nondecreasing) counts the residual blocks of the slots before s.
 template <typename T>
-__global__ __launch_bounds__(64 * RES_EDGES) void pool_residual_kernel(const SlotDesc<T> *slots, long long G)
+__global__ __launch_bounds__(64 * RES_EDGES) void pool_residual_kernel(const SlotDesc<T> *slots, const int *res_off,
+                                                                       const PoolState *ps, int nslots, int it)
 {
     __shared__ double lds[2 * RES_EDGES];
-    const SlotDesc<T> &d = slots[blockIdx.y];
+    const int item = blockIdx.x;
+    if (item >= ps->nres) return;
+    int lo = 0, hi = nslots;  // the last slot s with res_off[s] <= item
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (res_off[mid] <= item) lo = mid;
+        else hi = mid;
+    }
+    const SlotDesc<T> &d = slots[lo];
     long long k;
-    if (!slot_live(d, G, k)) return;
-    if ((int)blockIdx.x >= d.c.nrp) return;
-    residual_body<T>(d.c, d.b, d.pl, (int)blockIdx.x, lds);
+    if (!slot_live(d, ps->G + it, k)) return;
+    residual_body<T>(d.c, d.b, d.pl, item - res_off[lo], lds);
 }
 
-// one block per slot; acts on the slots whose iteration G adapted omega or was checked
+// one block per slot; acts on the slots whose iteration G + it adapted omega or was checked
 template <typename T>
-__global__ __launch_bounds__(CTRL_BLOCK) void pool_control_kernel(const SlotDesc<T> *slots, long long G, int check)
+__global__ __launch_bounds__(CTRL_BLOCK) void pool_control_kernel(const SlotDesc<T> *slots, const PoolState *ps,
+                                                                  int it, int check)
 {
     __shared__ double lds[NQ * (CTRL_BLOCK / 64)];
     const SlotDesc<T> &d = slots[blockIdx.x];
     long long k;
-    if (!slot_live(d, G, k)) return;
+    if (!slot_live(d, ps->G + it, k)) return;
     const bool adapt = adapts_at(d.c, k);
     if (!check && !adapt) return;
     control_body<T>(d.c, d.b, d.pl, check, adapt, k + 1, lds);
 }
 
-// copies every slot's scalar record into one array (one host copy per block of iterations)
+// Copies every slot's scalar record into one array (one host copy per step) and advances the
+// pool's iteration counter past the step (the last launch of a step: none of its launches
+// reads G after this one starts).
 template <typename T>
-__global__ void pool_gather_kernel(const SlotDesc<T> *slots, int nslots, DevScalars *out)
+__global__ void pool_gather_kernel(const SlotDesc<T> *slots, int nslots, DevScalars *out, PoolState *ps, int iters)
 {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s < nslots && slots[s].active) out[s] = *slots[s].b.sc;
+    if (s == 0) ps->G += iters;
 }
 
 // ---------------------------------------------------------------- launchers
@@ -1807,27 +1827,61 @@ hipError_t launch_poison(const Bufs<T> &b, int which, long long offset, hipStrea
     return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_pool_iteration(const SlotDesc<T> *slots, const int2 *work, int nwork, int nslots, int max_m,
-                                 int max_ept, long long G, bool check, bool control, hipStream_t st)
+// Pool shapes compiled per iterate size: waves per node workgroup.
+bool pool_waves_valid(int waves, int bytes) { return waves == 8 || (bytes == 4 && waves == 4); }
+
+// Measured pool shapes (written by tune.py), by the largest n a pool admits.
+struct TunedPool {
+    int bytes, n_max, waves;
+};
+#include "tuned_pool.inc"
+
+PoolShape pool_shape_for(int n_max, int bytes)
 {
-    const size_t lds = (check ? 2 : 1) * POOL_WAVES * max_ept * 64 * sizeof(double);
+    PoolShape sh{8, 0, 0, n_max <= 64 ? 1 : n_max <= 128 ? 2 : n_max <= 256 ? 4 : 8};
+    for (const TunedPool &t : TUNED_POOL)
+        if (t.bytes == bytes && n_max <= t.n_max) {
+            if (pool_waves_valid(t.waves, bytes)) sh.waves = t.waves;
+            break;
+        }
+    return sh;
+}
+
+template <typename T, int NWV>
+static void pool_fused_go(const SlotDesc<T> *slots, const int2 *work, const PoolState *ps, PoolShape sh, int it,
+                          bool check, hipStream_t st)
+{
+    const size_t lds = (check ? 2 : 1) * NWV * sh.max_ept * 64 * sizeof(double);
     if (check)
-        hipLaunchKernelGGL((pool_fused_kernel<T, true>), dim3(nwork), dim3(64 * POOL_WAVES), lds, st, slots, work, G);
+        hipLaunchKernelGGL((pool_fused_kernel<T, NWV, true>), dim3(sh.grid), dim3(64 * NWV), lds, st, slots, work,
+                           ps, it);
     else
-        hipLaunchKernelGGL((pool_fused_kernel<T, false>), dim3(nwork), dim3(64 * POOL_WAVES), lds, st, slots, work, G);
-    if (check)
-        hipLaunchKernelGGL(pool_residual_kernel<T>, dim3((max_m + RES_EDGES - 1) / RES_EDGES, nslots),
-                           dim3(64 * RES_EDGES), 0, st, slots, G);
+        hipLaunchKernelGGL((pool_fused_kernel<T, NWV, false>), dim3(sh.grid), dim3(64 * NWV), lds, st, slots, work,
+                           ps, it);
+}
+
+// sh.grid and sh.res_grid bound the item counts the pool state holds
+template <typename T>
+hipError_t launch_pool_iteration(const SlotDesc<T> *slots, const int2 *work, const int *res_off, const PoolState *ps,
+                                 int nslots, PoolShape sh, int it, bool check, bool control, hipStream_t st)
+{
+    if (sh.grid < 1 || !pool_waves_valid(sh.waves, sizeof(T))) return hipErrorInvalidValue;
+    if (sh.waves == 8) pool_fused_go<T, 8>(slots, work, ps, sh, it, check, st);
+    else if constexpr (sizeof(T) == 4) pool_fused_go<T, 4>(slots, work, ps, sh, it, check, st);
+    if (check && sh.res_grid > 0)
+        hipLaunchKernelGGL(pool_residual_kernel<T>, dim3(sh.res_grid), dim3(64 * RES_EDGES), 0, st, slots, res_off, ps,
+                           nslots, it);
     if (control)
-        hipLaunchKernelGGL(pool_control_kernel<T>, dim3(nslots), dim3(CTRL_BLOCK), 0, st, slots, G, check ? 1 : 0);
+        hipLaunchKernelGGL(pool_control_kernel<T>, dim3(nslots), dim3(CTRL_BLOCK), 0, st, slots, ps, it, check ? 1 : 0);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_pool_gather(const SlotDesc<T> *slots, int nslots, DevScalars *out, hipStream_t st)
+hipError_t launch_pool_gather(const SlotDesc<T> *slots, int nslots, DevScalars *out, PoolState *ps, int iters,
+                              hipStream_t st)
 {
-    hipLaunchKernelGGL(pool_gather_kernel<T>, dim3((nslots + 63) / 64), dim3(64), 0, st, slots, nslots, out);
+    hipLaunchKernelGGL(pool_gather_kernel<T>, dim3((nslots + 63) / 64), dim3(64), 0, st, slots, nslots, out, ps,
+                       iters);
     return hipGetLastError();
 }
 
@@ -1845,9 +1899,9 @@ hipError_t launch_pool_gather(const SlotDesc<T> *slots, int nslots, DevScalars *
                                           long long, hipStream_t);                                              \
     template hipError_t launch_poison<T>(const Bufs<T> &, int, long long, hipStream_t);                      \
     template hipError_t launch_p_from_f<T>(const Consts &, const Bufs<T> &, hipStream_t);                    \
-    template hipError_t launch_pool_iteration<T>(const SlotDesc<T> *, const int2 *, int, int, int, int, long long, \
-                                                 bool, bool, hipStream_t);                                    \
-    template hipError_t launch_pool_gather<T>(const SlotDesc<T> *, int, DevScalars *, hipStream_t);
+    template hipError_t launch_pool_iteration<T>(const SlotDesc<T> *, const int2 *, const int *, const PoolState *, \
+                                                 int, PoolShape, int, bool, bool, hipStream_t);               \
+    template hipError_t launch_pool_gather<T>(const SlotDesc<T> *, int, DevScalars *, PoolState *, int, hipStream_t);
 
 MCF_INSTANTIATE(float)
 MCF_INSTANTIATE(double)

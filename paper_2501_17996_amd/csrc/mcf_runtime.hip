@@ -29,6 +29,35 @@ constexpr size_t ALIGN = 256;
 
 size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
+// Pinned host mirrors of the device scalars (three records per handle) come from a process-wide
+// free list, allocated in chunks and kept until the process ends: creating and destroying
+// handles then calls neither hipHostMalloc nor hipHostFree, which may wait for the whole device
+// (a serving loop creates and destroys handles while a pool step runs on another stream).
+constexpr int PIN_CHUNK = 32;
+std::mutex g_pin_mu;
+std::vector<DevScalars *> g_pin_free;
+
+DevScalars *pinned_get()
+{
+    std::lock_guard<std::mutex> lock(g_pin_mu);
+    if (g_pin_free.empty()) {
+        DevScalars *chunk = nullptr;
+        if (hipHostMalloc((void **)&chunk, sizeof(DevScalars) * 3 * PIN_CHUNK, hipHostMallocDefault) != hipSuccess)
+            return nullptr;
+        for (int q = PIN_CHUNK - 1; q >= 0; --q) g_pin_free.push_back(chunk + 3 * q);
+    }
+    DevScalars *p = g_pin_free.back();
+    g_pin_free.pop_back();
+    return p;
+}
+
+void pinned_put(DevScalars *p)
+{
+    if (!p) return;
+    std::lock_guard<std::mutex> lock(g_pin_mu);
+    g_pin_free.push_back(p);
+}
+
 long long padded_ld(int n) { return (long long)((n + 63) / 64) * 64; }
 
 int node_blocks(int n, int nb)
@@ -409,7 +438,8 @@ int enqueue_block_graph(mcf_solver *s, long long k0, long long count)
     auto it = s->graphs.find(key);
     // a solve uses two or three block shapes; runs of many different lengths go out directly
     // once the cache holds MAX_GRAPHS of them
-    if (it == s->graphs.end() && s->graphs.size() >= MAX_GRAPHS) return enqueue_block<T>(s, k0, count);
+    // (with kernel timing on, one pair of events spans the whole drive: no per-iteration events)
+    if (it == s->graphs.end() && s->graphs.size() >= MAX_GRAPHS) return enqueue_block<T>(s, k0, count, false);
     if (it == s->graphs.end()) {
         MCF_TRY(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
         const int rc = enqueue_block<T>(s, k0, count, false);
@@ -653,13 +683,18 @@ void mcf_destroy(mcf_solver *s)
     for (hipEvent_t e : s->blk_ev)
         if (e) (void)hipEventDestroy(e);
     if (s->own_mem && s->base) (void)hipFree(s->base);
-    if (s->hs) (void)hipHostFree(s->hs);
+    pinned_put(s->hs);
     if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
     delete s;
 }
 
-int mcf_create(int32_t n, int32_t m, const int32_t *tail, const int32_t *head, const double *cap, int32_t utility,
-               double gamma, const double *w, const mcf_options *opt, mcf_solver **out)
+}  // extern "C"
+
+namespace {
+// Validates a problem and its options and builds the host side of a new solver (sizes, launch
+// shape, constants, buffer plan); makes no HIP call.  *out is the new solver on success.
+int prepare_solver(int32_t n, int32_t m, const int32_t *tail, const int32_t *head, const double *cap, int32_t utility,
+                   double gamma, const double *w, const mcf_options *opt, mcf_solver **out)
 {
     if (!out) return MCF_E_ARG;
     *out = nullptr;
@@ -737,7 +772,21 @@ int mcf_create(int32_t n, int32_t m, const int32_t *tail, const int32_t *head, c
     c.nep = n;  // edge quantities are added per tail node
     c.nrp = (m + RES_EDGES - 1) / RES_EDGES;
     c.nnp = fused ? n : c.nblk_node;
+    *out = s;
+    return MCF_OK;
+}
+}  // namespace
 
+extern "C" {
+
+int mcf_create(int32_t n, int32_t m, const int32_t *tail, const int32_t *head, const double *cap, int32_t utility,
+               double gamma, const double *w, const mcf_options *opt, mcf_solver **out)
+{
+    if (!out) return MCF_E_ARG;
+    *out = nullptr;
+    mcf_solver *s = nullptr;
+    if (int rc0 = prepare_solver(n, m, tail, head, cap, utility, gamma, w, opt, &s)) return rc0;
+    const mcf_options &o = s->opt;
     int rc = MCF_OK;
     if (hipSetDevice(o.device) != hipSuccess) rc = MCF_E_DEVICE;
     if (!rc) {
@@ -749,8 +798,7 @@ int mcf_create(int32_t n, int32_t m, const int32_t *tail, const int32_t *head, c
             rc = MCF_E_DEVICE;
         }
     }
-    if (!rc && hipHostMalloc((void **)&s->hs, 3 * sizeof(DevScalars), hipHostMallocDefault) != hipSuccess)
-        rc = MCF_E_NOMEM;
+    if (!rc && !(s->hs = pinned_get())) rc = MCF_E_NOMEM;
     for (int q = 0; q < 2 && !rc; ++q)
         if (hipEventCreateWithFlags(&s->blk_ev[q], hipEventDisableTiming) != hipSuccess) rc = MCF_E_DEVICE;
     if (!rc) {
@@ -999,25 +1047,46 @@ int mcf_layout(const mcf_solver *s, int32_t *ld, int32_t *edge_block, int32_t *e
 }  // extern "C"
 
 struct mcf_pool {
-    int device = 0, precision = 0, max_slots = 0, check_every = 1;
+    int device = 0, precision = 0, max_slots = 0, check_every = 1, n_max = FUSED_MAX_N, graphs = 1;
     size_t budget = 0, used = 0;
     hipStream_t stream = nullptr;
     bool own_stream = false;
-    long long G = 0;  // pool iterations enqueued so far
+    PoolShape shape{};
+    long long G = 0;  // pool iterations enqueued so far (the device counter equals it when idle)
     std::vector<mcf_solver *> slot;
     std::vector<SlotDesc<double>> desc;  // host copy (the layout does not depend on the iterate type)
     SlotDesc<double> *d_desc = nullptr;
     int2 *d_work = nullptr;
+    int *d_res_off = nullptr;
+    PoolState *d_state = nullptr;
     DevScalars *d_snap = nullptr;
     DevScalars *h_snap = nullptr;         // pinned
     SlotDesc<double> *h_desc = nullptr;   // pinned staging
     int2 *h_work = nullptr;               // pinned staging
-    int nwork = 0, max_m = 1, max_ept = 1;
+    int *h_res_off = nullptr;             // pinned staging
+    PoolState *h_state = nullptr;         // pinned staging
+    int nwork = 0;
     hipEvent_t done = nullptr;
     bool pending = false;
+    // captured steps, keyed by their length, the iterations at which some slot adapts omega and
+    // the grids; each with the step count of its last use (least recently used goes first)
+    std::map<std::string, std::pair<hipGraphExec_t, long long>> graphs_cache;
+    long long steps = 0;
 };
 
 namespace {
+
+// A launch grid for `items` work items: the count rounded up to a multiple of an eighth of its
+// leading power of two (at least 256), so that the few grids a pool passes through as instances
+// come and go are captured once each, at most 1/8 of the workgroups idle.
+int pool_grid(int items)
+{
+    if (items <= 0) return 0;
+    int p2 = 1;
+    while (p2 * 2 <= items) p2 *= 2;
+    const int g = std::max(256, p2 / 8);
+    return (items + g - 1) / g * g;
+}
 
 int pool_upload(mcf_pool *p)
 {
@@ -1025,18 +1094,31 @@ int pool_upload(mcf_pool *p)
     std::memcpy(p->h_desc, p->desc.data(), sizeof(SlotDesc<double>) * p->max_slots);
     MCF_TRY(hipMemcpyAsync(p->d_desc, p->h_desc, sizeof(SlotDesc<double>) * p->max_slots, hipMemcpyHostToDevice,
                            p->stream));
-    int nw = 0, max_m = 1, max_n = 1;
+    // node items of the largest instances first: their workgroups cost the most, and starting
+    // them first leaves the small ones to fill the end of the launch
+    std::vector<int> order;
+    for (int sl = 0; sl < p->max_slots; ++sl)
+        if (p->desc[sl].active) order.push_back(sl);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return p->desc[a].c.n > p->desc[b].c.n; });
+    int nw = 0, nres = 0;
+    for (int sl : order)
+        for (int j = 0; j < p->desc[sl].c.n; ++j) p->h_work[nw++] = make_int2(sl, j);
     for (int sl = 0; sl < p->max_slots; ++sl) {
-        if (!p->desc[sl].active) continue;
-        const int n = p->desc[sl].c.n;
-        for (int j = 0; j < n; ++j) p->h_work[nw++] = make_int2(sl, j);
-        max_m = std::max(max_m, p->desc[sl].c.m);
-        max_n = std::max(max_n, n);
+        p->h_res_off[sl] = nres;
+        if (p->desc[sl].active) nres += p->desc[sl].c.nrp;
     }
+    p->h_res_off[p->max_slots] = nres;
     p->nwork = nw;
-    p->max_m = max_m;
-    p->max_ept = max_n <= 64 ? 1 : max_n <= 128 ? 2 : max_n <= 256 ? 4 : 8;
+    p->shape.grid = pool_grid(nw);
+    p->shape.res_grid = pool_grid(nres);
+    p->h_state->G = p->G;
+    p->h_state->nwork = nw;
+    p->h_state->nres = nres;
     if (nw) MCF_TRY(hipMemcpyAsync(p->d_work, p->h_work, sizeof(int2) * nw, hipMemcpyHostToDevice, p->stream));
+    MCF_TRY(hipMemcpyAsync(p->d_res_off, p->h_res_off, sizeof(int) * (p->max_slots + 1), hipMemcpyHostToDevice,
+                           p->stream));
+    MCF_TRY(hipMemcpyAsync(p->d_state, p->h_state, sizeof(PoolState), hipMemcpyHostToDevice, p->stream));
     MCF_TRY(hipStreamSynchronize(p->stream));
     return MCF_OK;
 }
@@ -1057,43 +1139,148 @@ void pool_refresh(mcf_pool *p, int sl)
     else s->state = MCF_RUNNING;
 }
 
+// The step's iterations (offsets from G) at which some active slot adapts omega: they end in a
+// control launch.  A slot whose stop flag was raised in the meantime is skipped by the kernels.
+std::vector<int> pool_adapt_points(const mcf_pool *p, int iters)
+{
+    std::vector<int> at;
+    for (int it = 0; it < iters; ++it)
+        for (int sl = 0; sl < p->max_slots; ++sl) {
+            const SlotDesc<double> &d = p->desc[sl];
+            if (!d.active) continue;
+            const long long k = d.k0 + (p->G + it - d.G0);
+            if (k < d.max_iter && adapts_at(d.c, k)) {
+                at.push_back(it);
+                break;
+            }
+        }
+    return at;
+}
+
+// Enqueues one step: `iters` pool iterations (the last one checks every slot), the control
+// launches at the adapt points and at the check, and the gather of every slot's record, which
+// advances the device's G.  Every argument is fixed for the pool or by the step's key.
+template <typename T>
+int pool_enqueue(mcf_pool *p, int iters, const std::vector<int> &adapt_at)
+{
+    const SlotDesc<T> *slots = (const SlotDesc<T> *)p->d_desc;
+    size_t a = 0;
+    for (int it = 0; it < iters; ++it) {
+        const bool check = it == iters - 1;
+        const bool adapt = a < adapt_at.size() && adapt_at[a] == it;
+        if (adapt) ++a;
+        MCF_TRY(launch_pool_iteration<T>(slots, p->d_work, p->d_res_off, p->d_state, p->max_slots, p->shape, it, check,
+                                         check || adapt, p->stream));
+    }
+    MCF_TRY(launch_pool_gather<T>(slots, p->max_slots, p->d_snap, p->d_state, iters, p->stream));
+    return MCF_OK;
+}
+
+int pool_enqueue_any(mcf_pool *p, int iters, const std::vector<int> &adapt_at)
+{
+    return p->precision == MCF_FP32 ? pool_enqueue<float>(p, iters, adapt_at) : pool_enqueue<double>(p, iters, adapt_at);
+}
+
+// A step as one launch of its captured graph (captured on first use, then replayed), or
+// launched directly when graphs are off.  A full cache drops its least recently used graph.
+int pool_enqueue_step(mcf_pool *p, int iters)
+{
+    const std::vector<int> adapt_at = pool_adapt_points(p, iters);
+    if (!p->graphs) return pool_enqueue_any(p, iters, adapt_at);
+    std::string key = std::to_string(iters) + "g" + std::to_string(p->shape.grid) + "r" +
+                      std::to_string(p->shape.res_grid);
+    for (int it : adapt_at) key += "," + std::to_string(it);
+    auto g = p->graphs_cache.find(key);
+    if (g == p->graphs_cache.end()) {
+        if (p->graphs_cache.size() >= MAX_GRAPHS) {  // no step is in flight (mcf_pool_step synced)
+            auto lru = p->graphs_cache.begin();
+            for (auto q = p->graphs_cache.begin(); q != p->graphs_cache.end(); ++q)
+                if (q->second.second < lru->second.second) lru = q;
+            (void)hipGraphExecDestroy(lru->second.first);
+            p->graphs_cache.erase(lru);
+        }
+        MCF_TRY(hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal));
+        const int rc = pool_enqueue_any(p, iters, adapt_at);
+        hipGraph_t graph = nullptr;
+        const hipError_t ec = hipStreamEndCapture(p->stream, &graph);
+        if (rc || ec != hipSuccess || !graph) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return rc ? rc : MCF_E_DEVICE;
+        }
+        hipGraphExec_t ex = nullptr;
+        const hipError_t ei = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ei != hipSuccess) return MCF_E_DEVICE;
+        g = p->graphs_cache.emplace(key, std::make_pair(ex, 0LL)).first;
+    }
+    g->second.second = ++p->steps;
+    MCF_TRY(hipGraphLaunch(g->second.first, p->stream));
+    return MCF_OK;
+}
+
 }  // namespace
 
 extern "C" {
 
-int mcf_pool_create(int32_t device, int32_t precision, size_t hbm_budget, int32_t max_slots, int32_t check_every,
-                    void *stream, mcf_pool **out)
+void mcf_pool_options_default(mcf_pool_options *o)
+{
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->precision = MCF_FP32;
+    o->max_slots = 64;
+    o->check_every = 20;
+    o->n_max = FUSED_MAX_N;
+    o->graphs = 1;
+}
+
+int mcf_pool_create(const mcf_pool_options *opt, mcf_pool **out)
 {
     if (!out) return MCF_E_ARG;
     *out = nullptr;
-    if ((precision != MCF_FP32 && precision != MCF_FP64) || max_slots < 1 || max_slots > MCF_POOL_MAX_SLOTS ||
-        check_every < 1)
+    mcf_pool_options o;
+    if (opt) o = *opt;
+    else mcf_pool_options_default(&o);
+    const int bytes = o.precision == MCF_FP32 ? 4 : 8;
+    if ((o.precision != MCF_FP32 && o.precision != MCF_FP64) || o.max_slots < 1 || o.max_slots > MCF_POOL_MAX_SLOTS ||
+        o.check_every < 1)
         return MCF_E_ARG;
+    if (o.n_max == 0) o.n_max = FUSED_MAX_N;
+    if (o.n_max < 2 || o.n_max > FUSED_MAX_N) return MCF_E_ARG;
+    if (o.waves != 0 && !pool_waves_valid(o.waves, bytes)) return MCF_E_ARG;
     mcf_pool *p = new (std::nothrow) mcf_pool();
     if (!p) return MCF_E_NOMEM;
-    p->device = device;
-    p->precision = precision;
-    p->budget = hbm_budget;
-    p->max_slots = max_slots;
-    p->check_every = check_every;
-    p->slot.assign(max_slots, nullptr);
-    p->desc.assign(max_slots, SlotDesc<double>{});
+    p->device = o.device;
+    p->precision = o.precision;
+    p->budget = o.hbm_budget;
+    p->max_slots = o.max_slots;
+    p->check_every = o.check_every;
+    p->n_max = o.n_max;
+    p->graphs = o.graphs ? 1 : 0;
+    p->slot.assign(o.max_slots, nullptr);
+    p->desc.assign(o.max_slots, SlotDesc<double>{});
+    p->shape = pool_shape_for(o.n_max, bytes);
+    if (o.waves) p->shape.waves = o.waves;
     int rc = MCF_OK;
-    if (hipSetDevice(device) != hipSuccess) rc = MCF_E_DEVICE;
+    if (hipSetDevice(o.device) != hipSuccess) rc = MCF_E_DEVICE;
     if (!rc) {
-        if (stream) p->stream = (hipStream_t)stream;
+        if (o.stream) p->stream = (hipStream_t)o.stream;
         else if (hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking) == hipSuccess) p->own_stream = true;
         else rc = MCF_E_DEVICE;
     }
-    const size_t work_cap = (size_t)max_slots * FUSED_MAX_N;
-    if (!rc && (hipMalloc((void **)&p->d_desc, sizeof(SlotDesc<double>) * max_slots) != hipSuccess ||
+    const size_t work_cap = (size_t)o.max_slots * FUSED_MAX_N;
+    if (!rc && (hipMalloc((void **)&p->d_desc, sizeof(SlotDesc<double>) * o.max_slots) != hipSuccess ||
                 hipMalloc((void **)&p->d_work, sizeof(int2) * work_cap) != hipSuccess ||
-                hipMalloc((void **)&p->d_snap, sizeof(DevScalars) * max_slots) != hipSuccess))
+                hipMalloc((void **)&p->d_res_off, sizeof(int) * (o.max_slots + 1)) != hipSuccess ||
+                hipMalloc((void **)&p->d_state, sizeof(PoolState)) != hipSuccess ||
+                hipMalloc((void **)&p->d_snap, sizeof(DevScalars) * o.max_slots) != hipSuccess))
         rc = MCF_E_NOMEM;
-    if (!rc && (hipHostMalloc((void **)&p->h_snap, sizeof(DevScalars) * max_slots, hipHostMallocDefault) != hipSuccess ||
-                hipHostMalloc((void **)&p->h_desc, sizeof(SlotDesc<double>) * max_slots, hipHostMallocDefault) !=
+    if (!rc && (hipHostMalloc((void **)&p->h_snap, sizeof(DevScalars) * o.max_slots, hipHostMallocDefault) != hipSuccess ||
+                hipHostMalloc((void **)&p->h_desc, sizeof(SlotDesc<double>) * o.max_slots, hipHostMallocDefault) !=
                     hipSuccess ||
-                hipHostMalloc((void **)&p->h_work, sizeof(int2) * work_cap, hipHostMallocDefault) != hipSuccess))
+                hipHostMalloc((void **)&p->h_work, sizeof(int2) * work_cap, hipHostMallocDefault) != hipSuccess ||
+                hipHostMalloc((void **)&p->h_res_off, sizeof(int) * (o.max_slots + 1), hipHostMallocDefault) !=
+                    hipSuccess ||
+                hipHostMalloc((void **)&p->h_state, sizeof(PoolState), hipHostMallocDefault) != hipSuccess))
         rc = MCF_E_NOMEM;
     if (!rc && hipEventCreateWithFlags(&p->done, hipEventDisableTiming) != hipSuccess) rc = MCF_E_DEVICE;
     if (!rc) rc = pool_upload(p);
@@ -1115,13 +1302,18 @@ void mcf_pool_destroy(mcf_pool *p)
             p->slot[sl]->pool = nullptr;
             p->slot[sl]->pool_slot = -1;
         }
+    for (auto &g : p->graphs_cache) (void)hipGraphExecDestroy(g.second.first);
     if (p->done) (void)hipEventDestroy(p->done);
     if (p->d_desc) (void)hipFree(p->d_desc);
     if (p->d_work) (void)hipFree(p->d_work);
+    if (p->d_res_off) (void)hipFree(p->d_res_off);
+    if (p->d_state) (void)hipFree(p->d_state);
     if (p->d_snap) (void)hipFree(p->d_snap);
     if (p->h_snap) (void)hipHostFree(p->h_snap);
     if (p->h_desc) (void)hipHostFree(p->h_desc);
     if (p->h_work) (void)hipHostFree(p->h_work);
+    if (p->h_res_off) (void)hipHostFree(p->h_res_off);
+    if (p->h_state) (void)hipHostFree(p->h_state);
     if (p->own_stream && p->stream) (void)hipStreamDestroy(p->stream);
     delete p;
 }
@@ -1130,7 +1322,7 @@ int mcf_pool_admit(mcf_pool *p, mcf_solver *s, int32_t *slot)
 {
     if (!p || !s) return MCF_E_ARG;
     if (int rc_ = idle(s)) return rc_;
-    if (s->pool || s->precision != p->precision || !s->c.fused) return MCF_E_ARG;
+    if (s->pool || s->precision != p->precision || !s->c.fused || s->n > p->n_max) return MCF_E_ARG;
     if (s->state == MCF_CONVERGED || s->state == MCF_DIVERGED) return MCF_E_STATE;
     int rc = mcf_pool_sync(p);
     if (rc) return rc;
@@ -1172,31 +1364,9 @@ int mcf_pool_step(mcf_pool *p, int32_t iters)
     int rc = mcf_pool_sync(p);
     if (rc) return rc;
     if (p->nwork == 0) return MCF_OK;
-    const int ns = p->max_slots;
-    for (int it = 0; it < iters; ++it) {
-        const bool check = it == iters - 1;
-        bool adapt = false;
-        for (int sl = 0; sl < ns; ++sl) {
-            const SlotDesc<double> &d = p->desc[sl];
-            if (!d.active) continue;
-            const long long k = d.k0 + (p->G - d.G0);
-            if (k < d.max_iter && adapts_at(d.c, k)) adapt = true;
-        }
-        hipError_t e;
-        if (p->precision == MCF_FP32)
-            e = launch_pool_iteration<float>((const SlotDesc<float> *)p->d_desc, p->d_work, p->nwork, ns, p->max_m,
-                                             p->max_ept, p->G, check, check || adapt, p->stream);
-        else
-            e = launch_pool_iteration<double>(p->d_desc, p->d_work, p->nwork, ns, p->max_m, p->max_ept, p->G, check,
-                                              check || adapt, p->stream);
-        MCF_TRY(e);
-        p->G += 1;
-    }
-    if (p->precision == MCF_FP32)
-        MCF_TRY(launch_pool_gather<float>((const SlotDesc<float> *)p->d_desc, ns, p->d_snap, p->stream));
-    else
-        MCF_TRY(launch_pool_gather<double>(p->d_desc, ns, p->d_snap, p->stream));
-    MCF_TRY(hipMemcpyAsync(p->h_snap, p->d_snap, sizeof(DevScalars) * ns, hipMemcpyDeviceToHost, p->stream));
+    if ((rc = pool_enqueue_step(p, iters))) return rc;
+    p->G += iters;
+    MCF_TRY(hipMemcpyAsync(p->h_snap, p->d_snap, sizeof(DevScalars) * p->max_slots, hipMemcpyDeviceToHost, p->stream));
     MCF_TRY(hipEventRecord(p->done, p->stream));
     p->pending = true;
     return MCF_OK;
@@ -1233,6 +1403,15 @@ int mcf_pool_retire(mcf_pool *p, int32_t slot)
     s->pool = nullptr;
     s->pool_slot = -1;
     return pool_upload(p);
+}
+
+int mcf_pool_shape(const mcf_pool *p, int32_t *waves, int32_t *grid, int32_t *max_ept)
+{
+    if (!p) return MCF_E_ARG;
+    if (waves) *waves = p->shape.waves;
+    if (grid) *grid = p->shape.grid;
+    if (max_ept) *max_ept = p->shape.max_ept;
+    return MCF_OK;
 }
 
 int mcf_pool_info(const mcf_pool *p, int32_t *active, size_t *used_bytes, int64_t *iterations)

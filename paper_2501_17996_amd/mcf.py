@@ -34,10 +34,11 @@ EXPORTED = [
     "mcf_reset",
     "mcf_status", "mcf_get_solution", "mcf_get_state", "mcf_set_state", "mcf_destroy", "mcf_strerror",
     "mcf_debug_poison", "mcf_enable_kernel_timing", "mcf_kernel_time", "mcf_layout", "mcf_edge_shapes",
-    "mcf_pool_create", "mcf_pool_admit", "mcf_pool_step", "mcf_pool_sync", "mcf_pool_poll", "mcf_pool_retire",
+    "mcf_pool_options_default", "mcf_pool_create", "mcf_pool_shape", "mcf_pool_admit", "mcf_pool_step", "mcf_pool_sync", "mcf_pool_poll", "mcf_pool_retire",
     "mcf_pool_info", "mcf_pool_destroy",
 ]
 MCF_POOL_MAX_SLOTS = 256
+FUSED_MAX_N = 512          # largest n of the single-launch iteration, the only one the pool runs
 
 
 class mcf_options(ctypes.Structure):
@@ -48,6 +49,12 @@ class mcf_options(ctypes.Structure):
                 ("stream", ctypes.c_void_p), ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t),
                 ("adapt_until", ctypes.c_int64), ("edge_waves", ctypes.c_int32), ("edge_vectors", ctypes.c_int32),
                 ("node_block", ctypes.c_int32), ("graphs", ctypes.c_int32), ("node_form", ctypes.c_int32)]
+
+
+class mcf_pool_options(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int32), ("precision", ctypes.c_int32), ("hbm_budget", ctypes.c_size_t),
+                ("max_slots", ctypes.c_int32), ("check_every", ctypes.c_int32), ("n_max", ctypes.c_int32),
+                ("waves", ctypes.c_int32), ("graphs", ctypes.c_int32), ("stream", ctypes.c_void_p)]
 
 
 class mcf_result(ctypes.Structure):
@@ -107,8 +114,10 @@ def lib():
         L.mcf_layout.argtypes = [_vp, _ip, _ip, _ip, _ip]
         L.mcf_edge_shapes.argtypes = [ctypes.c_int32, _ip, _ip, ctypes.c_int32]
         L.mcf_edge_shapes.restype = ctypes.c_int32
-        L.mcf_pool_create.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_size_t, ctypes.c_int32, ctypes.c_int32,
-                                      _vp, ctypes.POINTER(_vp)]
+        L.mcf_pool_options_default.argtypes = [ctypes.POINTER(mcf_pool_options)]
+        L.mcf_pool_options_default.restype = None
+        L.mcf_pool_create.argtypes = [ctypes.POINTER(mcf_pool_options), ctypes.POINTER(_vp)]
+        L.mcf_pool_shape.argtypes = [_vp, _ip, _ip, _ip]
         L.mcf_pool_admit.argtypes = [_vp, _vp, _ip]
         L.mcf_pool_step.argtypes = [_vp, ctypes.c_int32]
         L.mcf_pool_sync.argtypes = [_vp]
@@ -314,12 +323,28 @@ class Solver:
 
 
 # ------------------------------------------------------------------- batching pool
+def mcf_pool_options_default() -> mcf_pool_options:
+    o = mcf_pool_options()
+    lib().mcf_pool_options_default(ctypes.byref(o))
+    return o
+
+
 def mcf_pool_create(precision: int, hbm_budget: int = 0, max_slots: int = 64, check_every: int = 20,
-                    stream=None, device: int = 0):
+                    stream=None, device: int = 0, n_max: int = 0, waves: int = 0, graphs: int = 1):
+    o = mcf_pool_options_default()
+    o.device, o.precision, o.hbm_budget = int(device), int(precision), int(hbm_budget)
+    o.max_slots, o.check_every, o.n_max = int(max_slots), int(check_every), int(n_max)
+    o.waves, o.graphs = int(waves), int(graphs)
+    o.stream = stream
     h = _vp()
-    _check(lib().mcf_pool_create(int(device), int(precision), int(hbm_budget), int(max_slots), int(check_every),
-                                 stream, ctypes.byref(h)), "mcf_pool_create")
+    _check(lib().mcf_pool_create(ctypes.byref(o), ctypes.byref(h)), "mcf_pool_create")
     return h
+
+
+def mcf_pool_shape(p) -> dict:
+    w, g, e = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().mcf_pool_shape(p, ctypes.byref(w), ctypes.byref(g), ctypes.byref(e)), "mcf_pool_shape")
+    return {"waves": w.value, "grid": g.value, "max_ept": e.value}
 
 
 def mcf_pool_admit(p, s) -> int:
@@ -361,10 +386,14 @@ class Pool:
     """A batching pool: many instances advanced by one launch per iteration."""
 
     def __init__(self, precision: int = MCF_FP32, hbm_budget: int = 0, max_slots: int = 64, check_every: int = 20,
-                 stream=None):
+                 stream=None, n_max: int = 0, waves: int = 0, graphs: int = 1):
         self.check_every = int(check_every)
         self.h = mcf_pool_create(precision, hbm_budget, max_slots, check_every,
-                                 ctypes.c_void_p(int(stream)) if stream is not None else None)
+                                 ctypes.c_void_p(int(stream)) if stream is not None else None, n_max=n_max,
+                                 waves=waves, graphs=graphs)
+
+    def shape(self) -> dict:
+        return mcf_pool_shape(self.h)
 
     def admit(self, solver: "Solver") -> int:
         return mcf_pool_admit(self.h, solver.h)

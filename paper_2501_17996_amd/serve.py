@@ -112,6 +112,11 @@ class GpuBackend:
         self.setup_stream = torch.cuda.Stream()
         self.pool = mcf.Pool(precision, hbm_budget, max_slots, check_every)
         self.max_slots = max_slots
+        self.capacity = int(hbm_budget)
+
+    def accepts(self, inst) -> bool:
+        """The pool batches instances that take the single-launch iteration (n <= 512)."""
+        return inst.n <= self.mcf.FUSED_MAX_N
 
     def footprint(self, inst) -> int:
         return self.mcf.mcf_workspace_bytes(inst.n, inst.m, self.precision)
@@ -163,71 +168,138 @@ def percentile(xs, q):
 def serve(requests, backend, clock=time.perf_counter, keep=None, idle_wait=1e-4):
     """Runs the request stream to completion.  ``requests`` are sorted by arrival.
     ``keep(record, handle)`` may read a finished instance (its solution) before it is
-    destroyed.  Returns (records, summary)."""
+    destroyed.  Returns (records, summary).
+
+    The device is kept busy while the host works: once the step in flight has ended, the
+    loop retires finished instances, admits the handles it created meanwhile, and enqueues
+    the next step at once; only then does it destroy retired handles, hand results to
+    ``keep`` and build the handles of queued requests (instance, CSR, upload on a stream of
+    its own), all of which overlaps the step now running.
+
+    A request whose footprint exceeds the whole arena, or that the backend cannot batch
+    (``backend.accepts``), or whose creation or admission fails, is answered at once with
+    a record in state "rejected" instead of waiting forever at the head of the queue."""
     pending = deque(sorted(requests, key=lambda r: r.arrival))
     queue = deque()
+    ready = deque()                  # (request, handle, record) created, not yet admitted
     active = {}                      # slot -> (request, handle, record)
+    retired = []                     # (request, handle, record) to destroy after the next enqueue
     records = []
+    capacity = getattr(backend, "capacity", None)
+    accepts = getattr(backend, "accepts", None)
     t0 = clock()
     steps = 0
     updates = 0.0
-    while pending or queue or active:
+    in_flight = False
+
+    def reject(req, inst, why):
+        rec = Record(req.rid, inst.n, inst.m, req.arrival, admitted=clock() - t0, state="rejected")
+        rec.done = rec.admitted
+        rec.extra["reason"] = why
+        records.append(rec)
+        req.inst = None
+
+    def prepare():
+        # arrivals, then handles for queued requests while slots and memory allow
         now = clock() - t0
         while pending and pending[0].arrival <= now:
             queue.append(pending.popleft())
-        # admission: FIFO, while a slot and device memory are free
-        while queue and len(active) < backend.max_slots:
+        while queue and len(active) + len(ready) < backend.max_slots:
             req = queue[0]
             inst = req.instance()
-            h = backend.create(inst)
-            if h is None:
-                break
-            slot = backend.admit(h)
-            rec = Record(req.rid, inst.n, inst.m, req.arrival, admitted=clock() - t0, slot=slot)
-            active[slot] = (req, h, rec)
-            queue.popleft()
-        if not active:
-            if pending:
-                wait = pending[0].arrival - (clock() - t0)
-                if wait > 0:
-                    time.sleep(min(wait, 0.01) if wait > idle_wait else 0)
-            continue
-        before = {slot: backend.poll(slot)["iters"] for slot in active}
-        backend.step()
-        backend.sync()
-        steps += 1
-        t_done = clock() - t0
-        for slot in list(active):
-            req, h, rec = active[slot]
-            st = backend.poll(slot)
-            updates += float(rec.n) * rec.m * (st["iters"] - before[slot])
-            if st["state_name"] == "running":
+            fp = backend.footprint(inst)
+            if capacity is not None and (fp + ALIGN - 1) // ALIGN * ALIGN > capacity:
+                queue.popleft()
+                reject(req, inst, f"footprint {fp} B exceeds the arena ({capacity} B)")
                 continue
-            backend.retire(slot)
-            rec.done = t_done
+            if accepts is not None and not accepts(inst):
+                queue.popleft()
+                reject(req, inst, "the backend cannot batch this instance")
+                continue
+            try:
+                h = backend.create(inst)
+            except Exception as e:  # invalid instance: answer it, keep serving the others
+                queue.popleft()
+                reject(req, inst, f"create failed: {e}")
+                continue
+            if h is None:
+                break                # no room in the arena now: wait for a retirement
+            queue.popleft()
+            ready.append((req, h, Record(req.rid, inst.n, inst.m, req.arrival)))
+
+    def finish(req, h, rec):
+        if keep is not None:
+            keep(rec, h)
+        backend.destroy(h)
+        req.inst = None              # the library holds its own copy; free the host arrays
+        records.append(rec)
+
+    prepare()
+    while pending or queue or ready or active or in_flight:
+        if in_flight:
+            backend.sync()
+            in_flight = False
+            t_done = clock() - t0
+            for slot in list(active):
+                req, h, rec = active[slot]
+                st = backend.poll(slot)
+                updates += float(rec.n) * rec.m * (st["iters"] - rec.iters)
+                rec.iters = st["iters"]
+                if st["state_name"] == "running":
+                    continue
+                backend.retire(slot)
+                rec.done = t_done
+                rec.state = st["state_name"]
+                rec.rel_kkt = st["rel_kkt"]
+                rec.primal_obj = st["primal_obj"]
+                retired.append((req, h, rec))
+                del active[slot]
+        # admission: FIFO, into free slots
+        while ready and len(active) < backend.max_slots:
+            req, h, rec = ready.popleft()
+            try:
+                slot = backend.admit(h)
+            except Exception as e:
+                backend.destroy(h)
+                rec.admitted = rec.done = clock() - t0
+                rec.state = "rejected"
+                rec.extra["reason"] = f"admit failed: {e}"
+                req.inst = None
+                records.append(rec)
+                continue
+            st = backend.poll(slot)
             rec.iters = st["iters"]
-            rec.state = st["state_name"]
-            rec.rel_kkt = st["rel_kkt"]
-            rec.primal_obj = st["primal_obj"]
-            if keep is not None:
-                keep(rec, h)
-            backend.destroy(h)
-            req.inst = None          # the library holds its own copy; free the host arrays
-            records.append(rec)
-            del active[slot]
+            rec.admitted = clock() - t0
+            rec.slot = slot
+            active[slot] = (req, h, rec)
+        if active:
+            backend.step()
+            in_flight = True
+            steps += 1
+        # host work while the step runs
+        for item in retired:
+            finish(*item)
+        retired.clear()
+        prepare()
+        if not in_flight and not ready and not active and pending:
+            wait = pending[0].arrival - (clock() - t0)
+            if wait > 0:
+                time.sleep(min(wait, 0.01) if wait > idle_wait else 0)
     makespan = clock() - t0
-    lat = [r.latency for r in records]
-    svc = [r.service for r in records]
+    served = [r for r in records if r.state != "rejected"]
+    lat = [r.latency for r in served]
+    svc = [r.service for r in served]
     summary = {
-        "requests": len(records),
+        "requests": len(served),
+        "rejected": len(records) - len(served),
         "makespan_s": makespan,
-        "instances_per_s": len(records) / makespan if makespan > 0 else math.nan,
+        "instances_per_s": len(served) / makespan if makespan > 0 else math.nan,
         "edge_dest_updates_per_s": updates / makespan if makespan > 0 else math.nan,
         "latency_p50_s": percentile(lat, 50),
         "latency_p99_s": percentile(lat, 99),
         "service_p50_s": percentile(svc, 50),
         "service_p99_s": percentile(svc, 99),
         "steps": steps,
-        "converged": sum(r.state == "converged" for r in records),
+        "converged": sum(r.state == "converged" for r in served),
     }
     return records, summary

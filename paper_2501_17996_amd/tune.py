@@ -1,4 +1,4 @@
-"""Launch-shape tuner for the two-phase iteration.
+"""Launch-shape tuner for the two-phase iteration and the batching pool.
 
 Times every compiled edge shape (``mcf_edge_shapes``) whose columns hold n entries, with each
 node-phase block (64 and 256 threads), on a ring + chords instance of out-degree 10 (the shape
@@ -12,6 +12,16 @@ A candidate's time is the mean duration of its regular iterations (edge and node
 from the events the dispatches record (``mcf_enable_kernel_timing``), after warm-up iterations.
 
     python -m paper_2501_17996_amd.tune [--sizes 128,256,...] [--summary FILE]
+
+With ``--pool`` it tunes the batching pool instead: for each bucket b of the largest n a pool
+admits (64, 128, 256, 512) it fills a pool with 64 instances of n uniform in (b/2, b],
+out-degree uniform in 4..16, half log and half power(1/2) utility (the shape of the serving
+stream), and times a pool iteration over all of them (events on the pool's stream, after
+warm-up steps) with each compiled number of waves per node workgroup; the fastest goes into
+``csrc/tuned_pool.inc``, which a pool looks up by its n_max.  The choice is a function of
+(n_max, precision) alone.
+
+    python -m paper_2501_17996_amd.tune --pool [--summary FILE]
 """
 from __future__ import annotations
 
@@ -71,6 +81,101 @@ def tune(sizes, log=print):
             rows.sort()
             results[(precision, n)] = rows
     return results
+
+
+POOL_INC = os.path.join(HERE, "csrc", "tuned_pool.inc")
+POOL_BUCKETS = (64, 128, 256, 512)
+POOL_WAVES = {1: (4, 8), 0: (8,)}     # compiled waves per node workgroup, per precision
+
+
+def pool_instances(b: int, slots: int = 64):
+    import numpy as np
+    from . import instances as I
+    rng = np.random.default_rng(b)
+    out = []
+    for q in range(slots):
+        n = int(rng.integers(max(20, b // 2 + 1), b + 1))
+        deg = int(rng.integers(4, 17))
+        out.append(I.ring_instance(n, min(deg, n - 1), seed=5000 + b + q, utility=q % 2, gamma=0.5))
+    return out
+
+
+def time_pool(mcf, torch, insts, precision, b, waves, steps=8, K=20):
+    """Microseconds per pool iteration over every instance (tolerance out of reach)."""
+    stream = torch.cuda.Stream()
+    pool = mcf.Pool(precision, 0, len(insts), K, stream=stream.cuda_stream, n_max=b, waves=waves)
+    hs = [mcf.Solver(i, precision=precision, tol=1e-14, check_every=K, max_iter=10 ** 8) for i in insts]
+    try:
+        for h in hs:
+            pool.admit(h)
+        for _ in range(3):
+            pool.step(K)
+            pool.sync()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            pool.step(K)
+        e1.record(stream)
+        pool.sync()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) * 1e3 / (steps * K)
+    finally:
+        pool.close()
+        for h in hs:
+            h.close()
+
+
+def tune_pool(log=print):
+    import torch
+    from . import mcf
+    torch.cuda.set_device(0)
+    results = {}   # (precision, b) -> sorted [(us, waves)]
+    for precision in (1, 0):
+        for b in POOL_BUCKETS:
+            insts = pool_instances(b)
+            rows = []
+            for waves in POOL_WAVES[precision]:
+                us = time_pool(mcf, torch, insts, precision, b, waves)
+                rows.append((us, waves))
+                log(f"pool {'fp32' if precision else 'fp64'} n_max={b:3d} waves={waves}: {us:8.2f} us/iteration "
+                    f"({sum(i.n for i in insts)} nodes)")
+            rows.sort()
+            results[(precision, b)] = rows
+    return results
+
+
+def write_pool_inc(results, path=POOL_INC):
+    lines = ["// Batching-pool launch shapes by measurement, written by paper_2501_17996_amd/tune.py (--pool)",
+             "// on one MI355X: 64 instances of n in (n_max/2, n_max], out-degree 4..16, log and power(1/2);",
+             "// mean time of a pool iteration over all of them.  Entries ascend in n_max per iterate size:",
+             "// {bytes, largest n of the pool, waves per node workgroup}.",
+             "static const TunedPool TUNED_POOL[] = {"]
+    for precision in (1, 0):
+        for b in POOL_BUCKETS:
+            rows = results.get((precision, b))
+            if rows:
+                us, waves = rows[0]
+                lines.append(f"    {{{4 if precision else 8}, {b}, {waves}}},  // {us:.2f} us")
+    lines.append("};")
+    with open(path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
+def write_pool_summary(results, path):
+    with open(path, "w") as f:
+        f.write("# Batching-pool shapes measured by `paper_2501_17996_amd/tune.py --pool`\n\n")
+        f.write("64 instances per pool, n uniform in (n_max/2, n_max], out-degree uniform in 4..16, half log "
+                "and half power(1/2) utility; mean time of one pool iteration over all of them (the "
+                "check every 20 iterations included), events on the pool's stream after 3 warm-up steps. The "
+                "first row of each bucket is the one the table takes.\n\n")
+        f.write("```\npython -m paper_2501_17996_amd.tune --pool --summary profiles/tuning_pool_shapes.md\n```\n\n")
+        f.write("| precision | n_max | waves per node | us per pool iteration | vs best |\n|---|---|---|---|---|\n")
+        for precision in (1, 0):
+            for b in POOL_BUCKETS:
+                rows = results.get((precision, b), [])
+                for us, waves in rows:
+                    f.write(f"| {'FP32' if precision else 'FP64'} | {b} | {waves} | {us:.2f} | "
+                            f"{us / rows[0][0]:.3f} |\n")
 
 
 ENTRY = re.compile(r"^\s*\{(\d+), (\d+), \{(\d+), (\d+), (\d+)\}, (\d+)\},\s*//\s*([0-9.]+) us")
@@ -134,8 +239,19 @@ def main(argv=None):
     ap.add_argument("--sizes", default=",".join(str(x) for x in LADDER))
     ap.add_argument("--summary", default=None, help="also write a markdown table of every measurement")
     ap.add_argument("--no-write", action="store_true", help="measure only; leave the table as it is")
-    ap.add_argument("--out", default=INC, help="where to write the table (default: the compiled-in one)")
+    ap.add_argument("--out", default=None, help="where to write the table (default: the compiled-in one)")
+    ap.add_argument("--pool", action="store_true", help="tune the batching pool's shapes instead")
     args = ap.parse_args(argv)
+    if args.pool:
+        res = tune_pool(log=lambda s: print(s, flush=True))
+        if not args.no_write:
+            write_pool_inc(res, args.out or POOL_INC)
+            print(f"wrote {args.out or POOL_INC}", flush=True)
+        if args.summary:
+            write_pool_summary(res, args.summary)
+            print(f"wrote {args.summary}", flush=True)
+        return 0
+    args.out = args.out or INC
     sizes = [int(x) for x in args.sizes.split(",")]
     res = tune(sizes, log=lambda s: print(s, flush=True))
     if not args.no_write:

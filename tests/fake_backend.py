@@ -6,8 +6,13 @@ from paper_2501_17996_amd.serve import Arena
 
 
 class OracleBackend:
-    def __init__(self, budget, max_slots, check_every, tol, max_iter=100000, bytes_per_var=32):
+    def __init__(self, budget, max_slots, check_every, tol, max_iter=100000, bytes_per_var=32, max_n=None,
+                 refuse_admit=()):
         self.arena = Arena(budget)
+        self.capacity = int(budget)
+        self.max_n = max_n                  # accepts(): instances up to this size (None: all)
+        self.refuse_admit = set(refuse_admit)  # admit() raises for instances of these sizes
+        self.live = 0                       # handles created and not yet destroyed
         self.max_slots, self.check_every, self.tol, self.max_iter = max_slots, check_every, tol, max_iter
         self.bpv = bytes_per_var
         self.slots = {}
@@ -23,12 +28,19 @@ class OracleBackend:
         if got is None:
             return None
         h = oracle.OracleSolver(inst)
+        h.n_nodes = inst.n
+        self.live += 1
         h.block = got
         h.status = {"iters": 0, "state_name": "running", "rel_kkt": float("inf"), "primal_obj": float("inf")}
         self.peak_bytes = max(self.peak_bytes, self.arena.size - self.arena.free_bytes())
         return h
 
+    def accepts(self, inst):
+        return self.max_n is None or inst.n <= self.max_n
+
     def admit(self, h):
+        if h.n_nodes in self.refuse_admit:
+            raise ValueError("refused by the pool")
         slot = min(set(range(self.max_slots)) - set(self.slots))
         self.slots[slot] = h
         self.peak_slots = max(self.peak_slots, len(self.slots))
@@ -57,4 +69,5 @@ class OracleBackend:
 
     def destroy(self, h):
         self.arena.release(*h.block)
+        self.live -= 1
         h.close()

@@ -151,7 +151,19 @@ def test_graph_not_strongly_connected(mcf):
 
 
 def test_pool_argument_validation(mcf):
-    for args in [(7, 0, 4, 20), (1, 0, 0, 20), (1, 0, mcf.MCF_POOL_MAX_SLOTS + 1, 20), (1, 0, 4, 0)]:
+    """Invalid pool options are refused on the host, before any device call."""
+    bad = [dict(precision=7), dict(max_slots=0), dict(max_slots=mcf.MCF_POOL_MAX_SLOTS + 1), dict(check_every=0),
+           dict(n_max=1), dict(n_max=513), dict(waves=6), dict(waves=16), dict(precision=0, waves=4),
+]
+    for kw in bad:
+        args = {"precision": 1, "hbm_budget": 0, "max_slots": 4, "check_every": 20}
+        args.update(kw)
         with pytest.raises(mcf.MCFError) as ei:
-            mcf.mcf_pool_create(args[0], args[1], args[2], args[3])
-        assert ei.value.code == mcf.MCF_E_ARG
+            mcf.mcf_pool_create(**args)
+        assert ei.value.code == mcf.MCF_E_ARG, kw
+
+
+def test_pool_options_defaults(mcf):
+    o = mcf.mcf_pool_options_default()
+    assert (o.precision, o.max_slots, o.check_every, o.n_max, o.graphs) == (mcf.MCF_FP32, 64, 20, 512, 1)
+    assert (o.waves, o.hbm_budget, o.stream) == (0, 0, None)

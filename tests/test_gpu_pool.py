@@ -2,16 +2,21 @@
 a mix (bitwise, the work of one instance never depends on another), continuous
 batching reproduces it, it agrees with the single-instance solver, and
 admission respects slots and the HBM budget."""
+import math
+import os
 import sys
 
 import numpy as np
 import pytest
 
+import oracle
 from paper_2501_17996_amd import instances as I
+from tests.test_gpu_parity import assert_infeasible_count_exact
 
 pytestmark = pytest.mark.gpu
 
 K = 20
+THREADS = max(1, min(16, os.cpu_count() or 1))
 
 
 @pytest.fixture(scope="module")
@@ -218,3 +223,209 @@ def test_pool_max_iter_and_slot_reuse(M):
     assert pool.admit(h2) == sl
     res = _drain(M, pool, [h2], [sl])
     assert res[sl][0]["state_name"] == "converged"
+
+
+def _relerr(a, b):
+    scale = max(float(np.max(np.abs(b))), 1e-300)
+    return float(np.max(np.abs(np.asarray(a) - np.asarray(b)))) / scale
+
+
+def test_pool_fp64_matches_oracle_at_checkpoints(M):
+    """The eight-instance mix in one FP64 pool against the oracle: at pool checkpoints
+    k = 20, 100 and 200 every instance's F^{k-1/2}, Y^k and omega match the oracle's to 1e-10
+    relative, and so do the metrics of the check that ends the step (objectives, gap,
+    residuals; the infeasible count exactly).  At each checkpoint the instances are retired,
+    read and admitted again, which must continue the same trajectories."""
+    insts = _mix()
+    pool = M.Pool(0, max_slots=len(insts), check_every=K)
+    hs = [_solver(M, inst, 0, 1e-13) for inst in insts]     # nothing stops before k = 200
+    live = {pool.admit(h): q for q, h in enumerate(hs)}
+    orcs = [oracle.OracleSolver(inst, threads=THREADS) for inst in insts]
+    done = 0
+    for k in (20, 100, 200):
+        while done < k:
+            pool.step(K)
+            pool.sync()
+            done += K
+        recs = {q: pool.poll(sl) for sl, q in live.items()}
+        for sl in list(live):
+            pool.retire(sl)
+        for q, inst in enumerate(insts):
+            O = orcs[q]
+            kk = int(O.get_state()[2]["k"])
+            O.run(k - kk - 1, check=False)
+            mo = O.step(check=True)
+            Fg, Yg, sg = hs[q].get_state()
+            Fo, Yo, so = O.get_state()
+            assert sg["k"] == so["k"] == k
+            ef, ey = _relerr(Fg, Fo), _relerr(Yg, Yo)
+            assert ef <= 1e-10 and ey <= 1e-10, (q, k, ef, ey)
+            assert sg["omega"] == pytest.approx(so["omega"], rel=1e-10)
+            g = recs[q]
+            assert g["iters"] == k and g["checked"] == 1
+            for key in ("primal_obj", "dual_obj"):
+                if math.isfinite(mo[key]):
+                    assert g[key] == pytest.approx(mo[key], rel=1e-10, abs=1e-12), (q, k, key)
+                else:
+                    assert g[key] == mo[key]
+            assert_infeasible_count_exact(g, mo, hs[q], O, what=f"pool instance {q} k {k}")
+            if math.isfinite(mo["rel_kkt"]):
+                assert abs(g["rel_kkt"] ** 2 - mo["rel_kkt"] ** 2) <= 1e-8 * mo["rel_kkt"] ** 2 + 1e-14
+            print(f"pool vs oracle: instance {q} n={inst.n} k={k} F {ef:.1e} Y {ey:.1e}", flush=True)
+        live = {pool.admit(h): q for q, h in enumerate(hs)}
+    pool.close()
+
+
+@pytest.mark.parametrize("step,waves", [(K, 8), (7, 8), (K, 4)])
+def test_pool_graphs_equal_direct_launches(M, step, waves):
+    """Steps replayed from captured graphs (keyed by the step length and the iterations where
+    some instance adapts omega) give bitwise the results of launching every kernel directly.
+    Steps of 7 iterations put the adaptations at several offsets within a step; instances
+    admitted at different pool iterations shift them further."""
+    insts = _mix()
+    out = []
+    for graphs in (1, 0):
+        pool = M.Pool(1, max_slots=len(insts), check_every=step, waves=waves, graphs=graphs)
+        assert pool.shape()["waves"] == waves
+        hs = [M.Solver(inst, precision=1, tol=1e-4, check_every=step, max_iter=60000) for inst in insts]
+        live, res, queue = {}, {}, list(range(len(insts)))
+        while queue or live:
+            if queue:                        # one admission per step: different G0 for each
+                q = queue.pop(0)
+                live[pool.admit(hs[q])] = q
+            pool.step(step)
+            pool.sync()
+            for sl in list(live):
+                st = pool.poll(sl)
+                if st["state_name"] != "running":
+                    pool.retire(sl)
+                    q = live.pop(sl)
+                    F, Y, _ = hs[q].get_state()
+                    res[q] = (st["iters"], st["primal_obj"], F, Y)
+        out.append(res)
+        pool.close()
+    for q in range(len(insts)):
+        a, b = out[0][q], out[1][q]
+        assert a[0] == b[0] and a[1] == b[1]
+        np.testing.assert_array_equal(a[2], b[2])
+        np.testing.assert_array_equal(a[3], b[3])
+
+
+def test_pool_four_waves_alone_equals_mix(M):
+    """The 4-wave node workgroup (FP32): alone and in the mix bitwise, and the same iterate
+    as the 8-wave shape up to the order of its sums."""
+    insts = _mix()
+    res = {}
+    for waves in (4, 8):
+        pool = M.Pool(1, max_slots=len(insts), check_every=K, waves=waves)
+        hs = [_solver(M, inst, 1, 1e-4) for inst in insts]
+        sls = [pool.admit(h) for h in hs]
+        mix = _drain(M, pool, hs, sls)
+        res[waves] = [mix[sl] for sl in sls]
+        pool.close()
+    for q in (0, 5):
+        pool = M.Pool(1, max_slots=1, check_every=K, waves=4)
+        h = _solver(M, insts[q], 1, 1e-4)
+        sl = pool.admit(h)
+        alone = _drain(M, pool, [h], [sl])[sl]
+        pool.close()
+        assert alone[0]["iters"] == res[4][q][0]["iters"]
+        np.testing.assert_array_equal(alone[1], res[4][q][1])
+        np.testing.assert_array_equal(alone[2], res[4][q][2])
+    for a, b in zip(res[4], res[8]):
+        assert a[0]["state_name"] == b[0]["state_name"] == "converged"
+        rel = abs(a[0]["primal_obj"] - b[0]["primal_obj"]) / max(1.0, abs(b[0]["primal_obj"]))
+        assert rel <= 1e-5
+
+
+def test_pool_n_max_limits_admission_and_shape(M):
+    pool = M.Pool(1, max_slots=2, check_every=K, n_max=128)
+    assert pool.shape()["max_ept"] == 2
+    big = _solver(M, _mix()[2], 1, 1e-4)         # n = 150
+    with pytest.raises(M.MCFError) as ei:
+        pool.admit(big)
+    assert ei.value.code == M.MCF_E_ARG
+    small = _solver(M, _mix()[1], 1, 1e-4)       # n = 70
+    sl = pool.admit(small)
+    res = _drain(M, pool, [small], [sl])
+    assert res[sl][0]["state_name"] == "converged"
+
+
+def test_serve_loop_on_the_gpu_equals_alone(M):
+    """serve() through the GPU backend: twelve requests of the serving stream on three slots,
+    admitted as slots free up.  Each request's result equals that instance run alone in a
+    one-slot pool of the same shape (iterations and objective exactly), and every arena block
+    is returned."""
+    from paper_2501_17996_amd.serve import GpuBackend, Request, serve
+    reqs = [I.serving_request(r) for r in range(12)]
+    budget = 3 * max(M.mcf_workspace_bytes(i.n, i.m, 1) for i in reqs) + (1 << 20)
+    be = GpuBackend(M.MCF_FP32, budget, 3, K, 1e-4, max_iter=60000, adapt_until=1000)
+    stream = [Request(r, 0.002 * r, reqs[r]) for r in range(12)]
+    records, summary = serve(stream, be)
+    assert summary["requests"] == 12 and summary["rejected"] == 0
+    assert be.arena.free == [(0, be.arena.size)]
+    be.close()
+    for rec in records:
+        inst = I.serving_request(rec.rid)
+        pool = M.Pool(1, max_slots=1, check_every=K)
+        h = M.Solver(inst, precision=1, tol=1e-4, check_every=K, max_iter=60000, adapt_until=1000)
+        sl = pool.admit(h)
+        st = _drain(M, pool, [h], [sl], limit=4000)[sl][0]
+        pool.close()
+        assert rec.state == st["state_name"] == "converged"
+        assert rec.iters == st["iters"] and rec.primal_obj == st["primal_obj"], rec.rid
+    print(f"serve on the GPU: {summary['requests']} requests, p50 {summary['latency_p50_s']:.3f} s", flush=True)
+
+
+def test_pool_graph_cache_eviction(M):
+    """Steps of every length from 1 to 40 make more step shapes than the graph cache holds: the
+    least recently used graphs are dropped and captured again, and the results stay bitwise
+    those of direct launches."""
+    insts = _mix()[:3]
+    out = []
+    for graphs in (1, 0):
+        pool = M.Pool(1, max_slots=3, check_every=K, graphs=graphs)
+        hs = [M.Solver(inst, precision=1, tol=1e-12, check_every=K, max_iter=10 ** 6) for inst in insts]
+        sls = [pool.admit(h) for h in hs]
+        for rep in range(2):
+            for L in range(1, 41):
+                pool.step(L)
+                pool.sync()
+        for sl in sls:
+            pool.retire(sl)
+        out.append([h.get_state()[:2] for h in hs])
+        pool.close()
+    for (Fa, Ya), (Fb, Yb) in zip(out[0], out[1]):
+        np.testing.assert_array_equal(Fa, Fb)
+        np.testing.assert_array_equal(Ya, Yb)
+
+
+def test_slow_instance_in_the_pool_tracks_the_oracle(M):
+    """The ring of 400 nodes with out-degree 4 (log utility, seed 44) converges slowly: its dual
+    residual is the last to close, and the oracle itself is still near rel_kkt 3e-3 at iteration
+    9000 with omega adapted throughout (about 1e-4 with omega frozen at 1000).  An earlier pool
+    test that required every instance to converge within its iteration limit failed on it.
+    Here the FP64 pool and the oracle agree on its first 1000 iterations (state to 1e-10, omega,
+    and rel_kkt), and both are still far from the tolerance there: the slow convergence is the
+    method's on this instance, not the pool's."""
+    inst = I.ring_instance(400, 4, seed=44, utility=0, gamma=0.5)
+    pool = M.Pool(0, max_slots=1, check_every=K)
+    h = M.Solver(inst, precision=0, tol=1e-4, check_every=K, max_iter=60000)
+    sl = pool.admit(h)
+    for _ in range(1000 // K):
+        pool.step(K)
+        pool.sync()
+    st = pool.poll(sl)
+    pool.retire(sl)
+    O = oracle.OracleSolver(inst, threads=THREADS)
+    O.run(999, check=False)
+    mo = O.step(check=True)
+    Fg, Yg, sg = h.get_state()
+    Fo, Yo, so = O.get_state()
+    assert sg["k"] == so["k"] == 1000 and st["iters"] == 1000
+    assert _relerr(Fg, Fo) <= 1e-10 and _relerr(Yg, Yo) <= 1e-10
+    assert sg["omega"] == pytest.approx(so["omega"], rel=1e-10)
+    assert abs(st["rel_kkt"] ** 2 - mo["rel_kkt"] ** 2) <= 1e-8 * mo["rel_kkt"] ** 2 + 1e-14
+    assert st["rel_kkt"] > 1e-2 and mo["rel_kkt"] > 1e-2
+    print(f"slow instance at k=1000: rel_kkt {st['rel_kkt']:.3e} (oracle {mo['rel_kkt']:.3e}), "
+          f"omega {sg['omega']:.4g}", flush=True)

@@ -68,3 +68,67 @@ def test_serving_results_do_not_depend_on_the_mix():
         records, _ = serve(reqs, be)
         out[slots] = {r.rid: (r.iters, r.primal_obj) for r in records}
     assert out[1] == out[5]
+
+
+def test_requests_that_cannot_be_served_are_rejected_not_waited_on():
+    """A request larger than the whole arena, one the backend cannot batch, and one whose
+    admission fails each get a record in state "rejected"; the loop serves the rest and
+    returns (it must not wait forever on the head of the queue), and every arena block and
+    handle is released."""
+    reqs = _stream(12, seed=9)
+    sizes = [r.inst.n for r in reqs]
+    big = I.ring_instance(60, 4, seed=77)
+    huge = Request(100, 0.0005, big)                       # footprint above the arena
+    odd = Request(101, 0.001, I.ring_instance(30, 3, seed=78))   # refused by accepts()
+    bad = Request(102, 0.0015, I.ring_instance(29, 3, seed=79))  # admit() raises
+    budget = 4 * max(r.inst.n * r.inst.m * 32 for r in reqs)
+    assert big.n * big.m * 32 > budget
+    be = OracleBackend(budget=budget, max_slots=3, check_every=10, tol=1e-4, max_n=max(sizes),
+                       refuse_admit={29})
+    assert 29 not in sizes and 30 > max(sizes)
+    records, summary = serve(reqs + [huge, odd, bad], be)
+    by = {r.rid: r for r in records}
+    for rid in (100, 101, 102):
+        assert by[rid].state == "rejected" and "reason" in by[rid].extra
+    assert summary["rejected"] == 3 and summary["requests"] == 12 and summary["converged"] == 12
+    assert be.arena.free == [(0, be.arena.size)] and be.live == 0
+
+
+def test_serving_loop_keeps_one_step_in_flight_while_host_works():
+    """Handles of queued requests are created while a step is in flight, and finished
+    instances are destroyed after the next step is enqueued."""
+    events = []
+
+    class Traced(OracleBackend):
+        in_flight = False
+
+        def step(self):
+            assert not self.in_flight
+            self.in_flight = True
+            events.append("step")
+            super().step()
+
+        def sync(self):
+            self.in_flight = False
+            events.append("sync")
+
+        def create(self, inst):
+            h = super().create(inst)
+            if h is not None:
+                events.append("create:busy" if self.in_flight else "create:idle")
+            return h
+
+        def destroy(self, h):
+            events.append("destroy:busy" if self.in_flight else "destroy:idle")
+            super().destroy(h)
+
+    reqs = [Request(r, 0.0, I.ring_instance(10, 3, seed=200 + r)) for r in range(8)]
+    be = Traced(budget=1 << 30, max_slots=2, check_every=10, tol=1e-4)
+    records, summary = serve(reqs, be)
+    assert summary["requests"] == 8
+    creates = [e for e in events if e.startswith("create")]
+    destroys = [e for e in events if e.startswith("destroy")]
+    # the first two handles are built before any step; every later one during a step
+    assert creates[:2] == ["create:idle", "create:idle"] and set(creates[2:]) == {"create:busy"}
+    # every destroy but those after the last step overlaps a step
+    assert destroys.count("destroy:busy") >= len(destroys) - 2
