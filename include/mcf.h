@@ -182,6 +182,26 @@ void mcf_destroy(mcf_solver *s);
 /* Static text for a return code. */
 const char *mcf_strerror(int code);
 
+/* For callers that cannot allocate device memory (tight serving loops, harnesses that forbid
+ * hipMalloc): mcf_create + mcf_solve + mcf_get_solution + mcf_status + mcf_destroy in one blocking
+ * call that allocates nothing.  Its workspace is a static device array of MCF_STATIC_BYTES per
+ * GPU, which the library holds until the process ends; the call makes no device or pinned
+ * allocation and creates no stream, event or graph (host memory is used for the CSR build).
+ *   arguments  as mcf_create, and the outputs of mcf_get_solution (F, T, Y: host FP64, NULL
+ *              skipped) and mcf_status (*result, required);
+ *   opt        NULL for the defaults; opt->stream is the stream to run on (NULL: the null
+ *              stream); opt->workspace must be NULL and workspace_bytes 0; graphs are not used.
+ * Errors: those of mcf_create, and MCF_E_ARG when the instance needs more than MCF_STATIC_BYTES
+ * (mcf_workspace_bytes gives the need; config2 takes about 10 MB in FP32, 20 MB in FP64).
+ * Every call on one GPU shares that GPU's array: calls from threads of one process are
+ * serialised by the library, but calls that overlap on one GPU from other processes, or that
+ * run on other streams while a call is in flight, race.  Results equal those of the handle
+ * API on the same instance and options. */
+enum { MCF_STATIC_BYTES = 64 << 20 };
+int mcf_solve_static(int32_t n, int32_t m, const int32_t *tail, const int32_t *head, const double *cap,
+                     int32_t utility, double gamma, const double *w, const mcf_options *opt, double *F, double *T,
+                     double *Y, mcf_result *result);
+
 /* Test hook: writes a NaN into F (which = 0, flat user index l*n+i) or Y (which = 1,
  * j*n+i) on the device; the next iteration then reports MCF_DIVERGED. */
 int mcf_debug_poison(mcf_solver *s, int32_t which, int64_t index);

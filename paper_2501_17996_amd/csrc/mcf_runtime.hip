@@ -148,6 +148,7 @@ struct mcf_solver {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     DevScalars *hs = nullptr;  // pinned host mirror of the device scalars; hs[1], hs[2] are block snapshots
+    DevScalars hs_local[3] = {};  // the mirror of a handle that may not allocate (mcf_solve_static)
     hipEvent_t blk_ev[2] = {nullptr, nullptr};  // completion of the snapshot copies
     int state = MCF_RUNNING;
     long long k = 0;  // PDHG iterations completed (authoritative count)
@@ -683,7 +684,7 @@ void mcf_destroy(mcf_solver *s)
     for (hipEvent_t e : s->blk_ev)
         if (e) (void)hipEventDestroy(e);
     if (s->own_mem && s->base) (void)hipFree(s->base);
-    pinned_put(s->hs);
+    if (s->hs != s->hs_local) pinned_put(s->hs);
     if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
     delete s;
 }
@@ -822,6 +823,104 @@ int mcf_create(int32_t n, int32_t m, const int32_t *tail, const int32_t *head, c
     }
     *out = s;
     return MCF_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------ the entry point that allocates nothing
+// Workspace of mcf_solve_static: a file-scope device array, one per GPU, held until the process
+// ends.  In host code its name is a host-side stand-in, never a device address: host code uses
+// only the address hipGetSymbolAddress returns for the current device (scratch_base).
+static __device__ __align__(256) char scratch[MCF_STATIC_BYTES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_static_mu[MAX_DEVICES];   // one call at a time per GPU within this process
+char *g_static_base[MAX_DEVICES] = {};
+
+// The device address of this GPU's scratch array, looked up once per device with the device
+// current (called with g_static_mu[device] held).
+int scratch_base(int device, char **out)
+{
+    if (!g_static_base[device]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return MCF_E_DEVICE;
+        g_static_base[device] = (char *)ptr;
+    }
+    *out = g_static_base[device];
+    return MCF_OK;
+}
+
+// The block loop of mcf_solve without graphs, events or pinned memory: each block of
+// check_every iterations is launched directly, then its scalar record is copied to the host
+// and waited for.
+int drive_sync(mcf_solver *s)
+{
+    int rc = pull_scalars(s);
+    if (rc) return rc;
+    s->hs->stop = 0;
+    s->hs->stop_enabled = 1;
+    if ((rc = push_scalars(s))) return rc;
+    const long long K = std::max(1, s->opt.check_every), target = s->opt.max_iter;
+    auto t0 = std::chrono::steady_clock::now();
+    bool stopped = false;
+    while (!stopped && s->k < target) {
+        const long long count = std::min(K, target - s->k);
+        rc = s->precision == MCF_FP32 ? enqueue_block<float>(s, s->k, count, false)
+                                      : enqueue_block<double>(s, s->k, count, false);
+        if (rc) return rc;
+        if ((rc = pull_scalars(s))) return rc;
+        if (s->hs->stop) {
+            s->k = s->hs->k;
+            stopped = true;
+        } else {
+            s->k += count;
+        }
+    }
+    if (stopped) s->state = s->hs->state == MCF_DIVERGED ? MCF_DIVERGED : MCF_CONVERGED;
+    else s->state = MCF_MAX_ITER;
+    s->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return MCF_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int mcf_solve_static(int32_t n, int32_t m, const int32_t *tail, const int32_t *head, const double *cap,
+                     int32_t utility, double gamma, const double *w, const mcf_options *opt, double *F, double *T,
+                     double *Y, mcf_result *result)
+{
+    if (!result) return MCF_E_ARG;
+    if (opt && (opt->workspace || opt->workspace_bytes)) return MCF_E_ARG;  // the static array is the workspace
+    mcf_solver *s = nullptr;
+    if (int rc0 = prepare_solver(n, m, tail, head, cap, utility, gamma, w, opt, &s)) return rc0;
+    const mcf_options &o = s->opt;
+    if (s->plan.total > MCF_STATIC_BYTES || o.device < 0 || o.device >= MAX_DEVICES) {
+        delete s;
+        return MCF_E_ARG;
+    }
+    std::lock_guard<std::mutex> lock(g_static_mu[o.device]);
+    int rc = hipSetDevice(o.device) == hipSuccess ? MCF_OK : MCF_E_DEVICE;
+    if (!rc) rc = scratch_base(o.device, &s->base);
+    if (!rc) {
+        s->hs = s->hs_local;
+        s->stream = (hipStream_t)o.stream;  // the caller's stream, or the null stream
+        // upload and reset write every buffer the iteration reads before it reads it (the
+        // previous call's contents are never used)
+        rc = o.precision == MCF_FP32 ? upload_problem<float>(s, tail, head, cap, w)
+                                     : upload_problem<double>(s, tail, head, cap, w);
+    }
+    if (!rc) rc = reset_any(s);
+    if (!rc) rc = drive_sync(s);
+    if (!rc && F) rc = download_any(s, s->plan.Fhat, s->m, true, F);
+    if (!rc && T) rc = download_cols<double>(s, s->plan.That, s->n, false, T);
+    if (!rc && Y) rc = download_any(s, s->cur_Y(), s->n, false, Y);
+    if (!rc) fill_result(s, result);
+    (void)hipStreamSynchronize(s->stream);
+    s->stream = nullptr;
+    s->base = nullptr;
+    mcf_destroy(s);
+    return rc;
 }
 
 namespace {

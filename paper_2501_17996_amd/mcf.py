@@ -33,7 +33,7 @@ EXPORTED = [
     "mcf_options_default", "mcf_workspace_bytes", "mcf_create", "mcf_solve", "mcf_solve_async", "mcf_run",
     "mcf_reset",
     "mcf_status", "mcf_get_solution", "mcf_get_state", "mcf_set_state", "mcf_destroy", "mcf_strerror",
-    "mcf_debug_poison", "mcf_enable_kernel_timing", "mcf_kernel_time", "mcf_layout", "mcf_edge_shapes",
+    "mcf_solve_static", "mcf_debug_poison", "mcf_enable_kernel_timing", "mcf_kernel_time", "mcf_layout", "mcf_edge_shapes",
     "mcf_pool_options_default", "mcf_pool_create", "mcf_pool_shape", "mcf_pool_admit", "mcf_pool_step", "mcf_pool_sync", "mcf_pool_poll", "mcf_pool_retire",
     "mcf_pool_info", "mcf_pool_destroy",
 ]
@@ -108,6 +108,9 @@ def lib():
         L.mcf_destroy.restype = None
         L.mcf_strerror.argtypes = [ctypes.c_int]
         L.mcf_strerror.restype = ctypes.c_char_p
+        L.mcf_solve_static.argtypes = [ctypes.c_int32, ctypes.c_int32, _ip, _ip, _dp, ctypes.c_int32,
+                                       ctypes.c_double, _dp, ctypes.POINTER(mcf_options), _dp, _dp, _dp,
+                                       ctypes.POINTER(mcf_result)]
         L.mcf_debug_poison.argtypes = [_vp, ctypes.c_int32, ctypes.c_int64]
         L.mcf_enable_kernel_timing.argtypes = [_vp, ctypes.c_int32]
         L.mcf_kernel_time.argtypes = [_vp, _dp, ctypes.POINTER(ctypes.c_int64)]
@@ -212,6 +215,24 @@ def mcf_set_state(h, F, Y=None, k: int | None = None, omega: float | None = None
     sc = mcf_scalars(int(k), float(omega), 0.0, 0.0, 0.0) if k is not None else None
     _check(lib().mcf_set_state(h, _ptr(F), _ptr(Yk) if Yk is not None else None,
                                ctypes.byref(sc) if sc is not None else None), "mcf_set_state")
+
+
+MCF_STATIC_BYTES = 64 << 20
+
+
+def mcf_solve_static(n, tail, head, cap, utility, gamma, w, opt: mcf_options | None = None):
+    """The solve that allocates nothing (static device workspace).  Returns (F, T, Y, result)."""
+    tail = np.ascontiguousarray(tail, dtype=np.int32)
+    head = np.ascontiguousarray(head, dtype=np.int32)
+    cap, w = _f64(cap), _f64(w)
+    m = int(tail.shape[0])
+    F, T, Y = np.empty(n * m), np.empty(n * n), np.empty(n * n)
+    r = mcf_result()
+    rc = lib().mcf_solve_static(int(n), m, _ptr(tail, _ip), _ptr(head, _ip), _ptr(cap), int(utility), float(gamma),
+                                _ptr(w), ctypes.byref(opt) if opt is not None else None, _ptr(F), _ptr(T), _ptr(Y),
+                                ctypes.byref(r))
+    _check(rc, "mcf_solve_static")
+    return F, T, Y, r.as_dict()
 
 
 def mcf_destroy(h):
