@@ -426,6 +426,13 @@ def main():
     from paper_2501_17996_amd import mcf
 
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        # kernels of known size for the counter runs: a 256 MiB fill (writes) and copy (reads and writes)
+        src = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     if args.workload == "pool":
         print(json.dumps(pool_leg(mcf, torch, args.slots, args.steps, args.check_every)), flush=True)
         return
@@ -437,12 +444,6 @@ def main():
     K = args.block if blocks else args.check_every
     S = mcf.Solver(inst, precision=prec, tol=tol, check_every=K, max_iter=200000,
                    stream=stream.cuda_stream, kernel_mode=args.kernel_mode, adapt_until=args.adapt_until)
-    if args.copy_calibration:
-        src = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda").fill_(1.0)
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
 
     def step():
         if blocks:

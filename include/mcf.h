@@ -74,7 +74,9 @@ typedef struct {
                                freezing omega after some iterations restores the constant-omega convergence proof */
     /* Launch shape of the two-phase iteration; 0 = the measured choice for this n and precision
      * (the table tune.py writes).  edge_waves: 1 = one wave per out-edge, eight out-edges of a
-     * tail at once; 4, 8 or 16 = that many waves per edge column, the out-edges of a tail in turn.
+     * tail at once; -1 = one wave per edge over a flat grid of eight-edge workgroups, the
+     * out-edge sums of F A^T gathered by the node phase; 4, 8 or 16 = that many waves per edge
+     * column, the out-edges of a tail in turn.
      * edge_vectors: 16-byte vectors per lane of a column.  The pair must be one that
      * mcf_edge_shapes lists and whose columns hold n entries (64 * waves * vectors * 16 / size
      * of the iterate), else MCF_E_ARG; both or neither are given.  node_block: 64 or 256
@@ -217,8 +219,8 @@ int mcf_enable_kernel_timing(mcf_solver *s, int32_t enable);
 int mcf_kernel_time(mcf_solver *s, double *edge_ms, int64_t *edge_launches);
 
 /* The two-phase edge shapes compiled into the library for this precision: writes up to cap
- * (waves, vectors) pairs (waves 1 = the concurrent form) and returns how many there are
- * (0 for an invalid precision). */
+ * (waves, vectors) pairs (waves 1 = the concurrent form, -1 = the flat form) and returns how
+ * many there are (0 for an invalid precision). */
 int32_t mcf_edge_shapes(int32_t precision, int32_t *waves, int32_t *vectors, int32_t cap);
 
 /* Internal sizes chosen at create: padded leading dimension, threads per edge column,

@@ -32,8 +32,10 @@ struct Consts {
     int nblk_node;         // node-phase blocks (partials per quantity)
     int node_block;        // threads per node-phase block (64 or 256)
     int fused;             // 1: node-centric single-launch iteration (n <= FUSED_MAX_N)
-    int nep, nnp;          // partials per edge quantity (dF, e, sup; one per tail node) and per node quantity
-    int edge_par;          // 1: out-edge sums grouped by wave (concurrent edge phase)
+    int nep, nnp;          // partials per edge quantity (dF, e, sup; one per tail node, or per workgroup of
+                           // the flat edge phase) and per node quantity
+    int edge_par;          // 1: out-edge sums grouped by wave (concurrent edge phase); 2: flat edge phase
+                           // (out-edge sums gathered by the node phase)
     int node_latency;      // 1: regular node launches in the latency form (F within NODE_LATENCY_BYTES)
     int nrp;               // partials of the residual pass (a, b; one per RES_EDGES edges)
 };
@@ -96,7 +98,8 @@ struct Bufs {
 // wpe == 1 a 256-thread block carries 4 tail nodes, one per wave.
 // par == 1: the tail's out-edges are projected concurrently, one wave per edge in an 8-wave
 // workgroup (a whole column per wave: n <= 64 * ept * 16 / bytes), and the out-edge sums are
-// added per wave and then over the waves in wave order.
+// added per wave and then over the waves in wave order.  par == 2: flat, one wave per edge
+// over a grid of 8-edge workgroups, no out-edge sums (the node phase gathers the out-edges).
 struct EdgeShape {
     int wpe, ept, par;
 };

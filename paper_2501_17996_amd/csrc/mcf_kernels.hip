@@ -626,12 +626,142 @@ __global__ __launch_bounds__(WPE == 1 ? 256 : 64 * WPE) void edge_kernel(Consts 
     }
 }
 
+// One edge column projected by one wave (n <= 64 * NV * VEC), with wave-level reductions only:
+// q = F[:,e] + alpha (Y[:,head] - Y[:,tail]), the multiplier mu by the warm-started active-set
+// search of edge_kernel, F <- rho Fhat + (1 - rho) F.  With OUTSUM the new column is added (in
+// the iterate type) into this lane's slice `so` of the wave's out-edge sum in LDS.  Adds the
+// edge's ||dF||^2, ||D||^2 and support term c_l (max_i (Y A)_il)_+ to the wave's totals.
+template <typename T, int NV, bool CHECK, bool PARTIAL, bool OUTSUM>
+__device__ __forceinline__ void wave_edge(const Consts &c, const Bufs<T> &b, int e, const T *yt, T ta, T *so,
+                                          double &dF_w, double &e_w, double &sup_w)
+{
+    constexpr int VEC = Vec<T>::N;
+    const int t = threadIdx.x & 63;
+    const int n = c.n;
+    const long long ld = c.ld;
+    const double rho = c.rho, omr = 1.0 - c.rho;
+    const T *yh = b.Y + (long long)__builtin_amdgcn_readfirstlane(b.head[e]) * ld;
+    T *f = b.F + (long long)e * ld;
+    const double cap = b.cap[e];
+    const double mu0 = b.mu[e];
+    T fo[NV][VEC], q[NV][VEC], bh[NV][VEC], bt[NV][VEC];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        const int i = (v * 64 + t) * VEC;
+        const int ic = i < n ? i : 0;
+        vload_nt(f + ic, fo[v]);
+        vload_nt(yh + ic, bh[v]);
+        vload(yt + ic, bt[v]);
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        const bool ok = (v * 64 + t) * VEC < n;
+#pragma unroll
+        for (int u = 0; u < VEC; ++u) {
+            q[v][u] = ok ? fo[v][u] + ta * (bh[v][u] - bt[v][u]) : T(0);
+            fo[v][u] = ok ? fo[v][u] : T(0);
+        }
+    }
+    auto support_sum = [&](T thr, double &s, int &cnt) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            T part = T(0);
+#pragma unroll
+            for (int u = 0; u < VEC; ++u) {
+                const bool in = q[v][u] > thr;
+                if (in) part += q[v][u];
+                cnt += wave_count(in);
+            }
+            s += (double)part;
+        }
+    };
+    const T thr0 = below(mu0, T(0));
+    double sp = 0.0, sw = 0.0;
+    int cp = 0, cw = 0;
+    support_sum(T(0), sp, cp);
+    support_sum(thr0, sw, cw);
+    wave_sum2(sp, sw);
+    double mu = 0.0;
+    if (sp > cap) {
+        mu = (sp - cap) * rcp_of(b.rcp, cp);
+        int prev = cp;  // mu came from S' = {q > 0}, a superset of {q > mu}
+        if (cw > 0) {
+            const double mw = (sw - cap) * rcp_of(b.rcp, cw);
+            if (mw > mu) {
+                mu = mw;
+                prev = mw >= mu0 ? cw : 0x7fffffff;  // {q > mu0} contains {q > mw} only if mw >= mu0
+            }
+        }
+        // each pass counts the support first; only a support that shrank needs its sum
+        for (int pass = 0; pass <= n; ++pass) {
+            const T thr = below(mu, T(0));
+            int cnt = 0;
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+#pragma unroll
+                for (int u = 0; u < VEC; ++u) cnt += wave_count(q[v][u] > thr);
+            if (cnt >= prev) break;
+            double s = 0.0;
+            int dummy = 0;
+            support_sum(thr, s, dummy);
+            s = wave_sum(s);
+            mu = (s - cap) * rcp_of(b.rcp, cnt);
+            prev = cnt;
+        }
+    }
+    double dsum = 0.0, esum = 0.0, gmax = -INFINITY;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        const int i = (v * 64 + t) * VEC;
+        if (i < n) {
+            T fn[VEC], fhv[VEC], dv[VEC], acc[VEC];
+            if (OUTSUM) vload(so + v * 64 * VEC, acc);
+#pragma unroll
+            for (int u = 0; u < VEC; ++u) {
+                T fov = fo[v][u];
+                asm volatile("" : "+v"(fov));
+                const double fod = (double)fov;
+                const double fh = fmax((double)q[v][u] - mu, 0.0);
+                fn[u] = (T)(rho * fh + omr * fod);
+                if (OUTSUM) acc[u] += fn[u];
+                if (PARTIAL) {
+                    const double d = (double)fn[u] - fod;
+                    dsum += d * d;
+                }
+                if (CHECK) {
+                    fhv[u] = (T)fh;
+                    dv[u] = (T)(fh - (double)q[v][u]);
+                    esum += (double)dv[u] * (double)dv[u];
+                }
+            }
+            if (OUTSUM) vstore(so + v * 64 * VEC, acc);
+            vstore_nt(f + i, fn);
+            if (CHECK) {
+                vstore_nt(b.Fhat + (long long)e * ld + i, fhv);
+                vstore_nt(b.D + (long long)e * ld + i, dv);
+#pragma unroll
+                for (int u = 0; u < VEC; ++u)
+                    if (i + u < n) gmax = fmax(gmax, (double)(bh[v][u] - bt[v][u]));
+            }
+        }
+    }
+    if (PARTIAL) dsum = wave_sum(dsum);
+    if (CHECK) {
+        esum = wave_sum(esum);
+        gmax = wave_max(gmax);
+    }
+    if (t == 0) b.mu[e] = mu;
+    dF_w += dsum;
+    e_w += esum;
+    if (CHECK) sup_w += cap * fmax(gmax, 0.0);  // c_l (max_i (Y A)_il)_+
+}
+
 // Concurrent edge phase for columns that fit one wave (n <= 64 * NV * VEC): workgroup =
 // tail node t with EDGE_PAR_WAVES waves; wave w projects the out-edges e0 + w, e0 + w + NW, ...
-// with wave-level reductions only (the search of edge_kernel), so the waves never wait for
-// each other inside the loop.  Each wave adds its new columns into its own out-sum (in the
-// iterate type, in its edge order); the sums are then added over the waves in wave order
-// through LDS into Sout[:,t].  Partials per tail: wave totals added in wave order.
+// with wave-level reductions only (wave_edge), so the waves never wait for each other inside
+// the loop.  Each wave adds its new columns into its own out-sum (in the iterate type, in its
+// edge order); the sums are then added over the waves in wave order through LDS into
+// Sout[:,t].  Partials per tail: wave totals added in wave order.
 template <typename T, int NV, bool CHECK, bool PARTIAL>
 __global__ __launch_bounds__(64 * EDGE_PAR_WAVES) __attribute__((amdgpu_waves_per_eu(NV == 4 && !CHECK ? 6 : 1)))
 void edge_kernel_par(Consts c, Bufs<T> b, PartLayout pl)
@@ -649,7 +779,6 @@ void edge_kernel_par(Consts c, Bufs<T> b, PartLayout pl)
     const long long ld = c.ld;
     const T ta = (T)b.sc->alpha;
     const T *yt = b.Y + (long long)tn * ld;
-    const double rho = c.rho, omr = 1.0 - c.rho;
     const int e0 = b.out_off[tn], e1 = b.out_off[tn + 1];
     // this wave's out-edge sum lives in its own slice of sol (registers are what limit how many
     // workgroups a CU holds; each lane touches only its own entries until the barrier)
@@ -662,122 +791,7 @@ void edge_kernel_par(Consts c, Bufs<T> b, PartLayout pl)
         for (int v = 0; v < NV; ++v) vstore(so + v * 64 * VEC, z);
     }
     double dF_w = 0.0, e_w = 0.0, sup_w = 0.0;
-    for (int e = e0 + w; e < e1; e += NW) {
-        const T *yh = b.Y + (long long)__builtin_amdgcn_readfirstlane(b.head[e]) * ld;
-        T *f = b.F + (long long)e * ld;
-        const double cap = b.cap[e];
-        const double mu0 = b.mu[e];
-        T fo[NV][VEC], q[NV][VEC], bh[NV][VEC], bt[NV][VEC];
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            const int i = (v * 64 + t) * VEC;
-            const int ic = i < n ? i : 0;
-            vload_nt(f + ic, fo[v]);
-            vload_nt(yh + ic, bh[v]);
-            vload(yt + ic, bt[v]);
-        }
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            const bool ok = (v * 64 + t) * VEC < n;
-#pragma unroll
-            for (int u = 0; u < VEC; ++u) {
-                q[v][u] = ok ? fo[v][u] + ta * (bh[v][u] - bt[v][u]) : T(0);
-                fo[v][u] = ok ? fo[v][u] : T(0);
-            }
-        }
-        auto support_sum = [&](T thr, double &s, int &cnt) {
-#pragma unroll
-            for (int v = 0; v < NV; ++v) {
-                T part = T(0);
-#pragma unroll
-                for (int u = 0; u < VEC; ++u) {
-                    const bool in = q[v][u] > thr;
-                    if (in) part += q[v][u];
-                    cnt += wave_count(in);
-                }
-                s += (double)part;
-            }
-        };
-        const T thr0 = below(mu0, T(0));
-        double sp = 0.0, sw = 0.0;
-        int cp = 0, cw = 0;
-        support_sum(T(0), sp, cp);
-        support_sum(thr0, sw, cw);
-        wave_sum2(sp, sw);
-        double mu = 0.0;
-        if (sp > cap) {
-            mu = (sp - cap) * rcp_of(b.rcp, cp);
-            int prev = cp;  // mu came from S' = {q > 0}, a superset of {q > mu}
-            if (cw > 0) {
-                const double mw = (sw - cap) * rcp_of(b.rcp, cw);
-                if (mw > mu) {
-                    mu = mw;
-                    prev = mw >= mu0 ? cw : 0x7fffffff;  // {q > mu0} contains {q > mw} only if mw >= mu0
-                }
-            }
-            // each pass counts the support first; only a support that shrank needs its sum
-            for (int pass = 0; pass <= n; ++pass) {
-                const T thr = below(mu, T(0));
-                int cnt = 0;
-#pragma unroll
-                for (int v = 0; v < NV; ++v)
-#pragma unroll
-                    for (int u = 0; u < VEC; ++u) cnt += wave_count(q[v][u] > thr);
-                if (cnt >= prev) break;
-                double s = 0.0;
-                int dummy = 0;
-                support_sum(thr, s, dummy);
-                s = wave_sum(s);
-                mu = (s - cap) * rcp_of(b.rcp, cnt);
-                prev = cnt;
-            }
-        }
-        double dsum = 0.0, esum = 0.0, gmax = -INFINITY;
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            const int i = (v * 64 + t) * VEC;
-            if (i < n) {
-                T fn[VEC], fhv[VEC], dv[VEC], acc[VEC];
-                vload(so + v * 64 * VEC, acc);
-#pragma unroll
-                for (int u = 0; u < VEC; ++u) {
-                    T fov = fo[v][u];
-                    asm volatile("" : "+v"(fov));
-                    const double fod = (double)fov;
-                    const double fh = fmax((double)q[v][u] - mu, 0.0);
-                    fn[u] = (T)(rho * fh + omr * fod);
-                    acc[u] += fn[u];
-                    if (PARTIAL) {
-                        const double d = (double)fn[u] - fod;
-                        dsum += d * d;
-                    }
-                    if (CHECK) {
-                        fhv[u] = (T)fh;
-                        dv[u] = (T)(fh - (double)q[v][u]);
-                        esum += (double)dv[u] * (double)dv[u];
-                    }
-                }
-                vstore(so + v * 64 * VEC, acc);
-                vstore_nt(f + i, fn);
-                if (CHECK) {
-                    vstore_nt(b.Fhat + (long long)e * ld + i, fhv);
-                    vstore_nt(b.D + (long long)e * ld + i, dv);
-#pragma unroll
-                    for (int u = 0; u < VEC; ++u)
-                        if (i + u < n) gmax = fmax(gmax, (double)(bh[v][u] - bt[v][u]));
-                }
-            }
-        }
-        if (PARTIAL) dsum = wave_sum(dsum);
-        if (CHECK) {
-            esum = wave_sum(esum);
-            gmax = wave_max(gmax);
-        }
-        if (t == 0) b.mu[e] = mu;
-        dF_w += dsum;
-        e_w += esum;
-        if (CHECK) sup_w += cap * fmax(gmax, 0.0);  // c_l (max_i (Y A)_il)_+
-    }
+    for (int e = e0 + w; e < e1; e += NW) wave_edge<T, NV, CHECK, PARTIAL, true>(c, b, e, yt, ta, so, dF_w, e_w, sup_w);
     // out-edge sums over the waves, in wave order
     if (t == 0) {
         red[w] = dF_w;
@@ -804,6 +818,50 @@ void edge_kernel_par(Consts c, Bufs<T> b, PartLayout pl)
         if (CHECK) {
             b.part[pl.e + tn] = bb;
             b.part[pl.sup + tn] = cc;
+        }
+    }
+}
+
+// Flat edge phase for columns that fit one wave: workgroup b = edges b NW .. b NW + NW - 1 (the
+// internal order, sorted by tail, so the edges of a workgroup mostly share their tail column),
+// one wave per edge, nothing shared between the waves: no projection waits for another edge,
+// and no tail's out-edges form a second round.  The out-edge sums are left to the node phase,
+// which gathers the out-edges of F as well as the in-edges.  Partials per workgroup: wave
+// totals added in wave order.
+template <typename T, int NV, bool CHECK, bool PARTIAL>
+__global__ __launch_bounds__(64 * EDGE_PAR_WAVES) void edge_kernel_flat(Consts c, Bufs<T> b, PartLayout pl)
+{
+    constexpr int NW = EDGE_PAR_WAVES;
+    __shared__ double red[3 * NW];
+    if (b.sc->stop) return;
+    const int blk = xcd_item(blockIdx.x, c.nep);
+    if (blk >= c.nep) return;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), t = threadIdx.x & 63;
+    const int e = blk * NW + w;
+    double dF_w = 0.0, e_w = 0.0, sup_w = 0.0;
+    if (e < c.m) {
+        const T *yt = b.Y + (long long)__builtin_amdgcn_readfirstlane(b.tail[e]) * c.ld;
+        wave_edge<T, NV, CHECK, PARTIAL, false>(c, b, e, yt, (T)b.sc->alpha, nullptr, dF_w, e_w, sup_w);
+    }
+    if (!PARTIAL && !CHECK) return;
+    if (t == 0) {
+        red[w] = dF_w;
+        red[NW + w] = e_w;
+        red[2 * NW + w] = sup_w;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = 0.0, bb = 0.0, cc = 0.0;
+#pragma unroll
+        for (int ww = 0; ww < NW; ++ww) {
+            a += red[ww];
+            bb += red[NW + ww];
+            cc += red[2 * NW + ww];
+        }
+        if (PARTIAL) b.part[pl.dF + blk] = a;
+        if (CHECK) {
+            b.part[pl.e + blk] = bb;
+            b.part[pl.sup + blk] = cc;
         }
     }
 }
@@ -868,6 +926,15 @@ __device__ __forceinline__ double p_entry(const T *X, const int *in_edge, int i0
     return gather_in<T, WIDE>(X, in_edge, i0, i1, ld, i) - (double)sout;
 }
 
+// (F A^T)_ij when the edge phase leaves the out-edge sums to the node phase (flat edge phase):
+// both gathers in FP64, the in-edges first.
+template <typename T, bool WIDE = false>
+__device__ __forceinline__ double p_entry_flat(const T *X, const int *in_edge, int i0, int i1, int o0, int o1,
+                                               long long ld, int i)
+{
+    return gather_in<T, WIDE>(X, in_edge, i0, i1, ld, i) - gather_out<T>(X, o0, o1, ld, i);
+}
+
 // LAT: the latency form (regular launches of instances whose F is within NODE_LATENCY_BYTES).
 template <typename T, int NB, int UTIL, bool CHECK, bool PARTIAL, bool LAT>
 __global__ __launch_bounds__(NB) void node_kernel(Consts c, Bufs<T> b, PartLayout pl)
@@ -886,17 +953,20 @@ __global__ __launch_bounds__(NB) void node_kernel(Consts c, Bufs<T> b, PartLayou
         const long long x = (long long)j * ld + i;
         // P' = F_new A^T; V = Fbar A^T = (2/rho) P' - ((2 - rho)/rho) P
         double pn, po, y, w;
+        const bool flat = c.edge_par == 2;  // the out-edge sum is gathered here too
         if (LAT) {
             // this entry's own operands first, so that their loads are in flight during the
             // gather (after the store to P the compiler could not move them above it)
-            const T sout = b.Sout[x], pot = b.P[x], yt = b.Y[x], wt = b.W[x];
-            pn = p_entry<T, true>(b.F, b.in_edge, i0, i1, sout, ld, i);
+            const T sout = flat ? T(0) : b.Sout[x], pot = b.P[x], yt = b.Y[x], wt = b.W[x];
+            pn = flat ? p_entry_flat<T, true>(b.F, b.in_edge, i0, i1, b.out_off[j], b.out_off[j + 1], ld, i)
+                      : p_entry<T, true>(b.F, b.in_edge, i0, i1, sout, ld, i);
             po = (double)pot;
             y = (double)yt;
             w = (double)wt;
             b.P[x] = (T)pn;
         } else {
-            pn = p_entry<T>(b.F, b.in_edge, i0, i1, b.Sout[x], ld, i);
+            pn = flat ? p_entry_flat<T>(b.F, b.in_edge, i0, i1, b.out_off[j], b.out_off[j + 1], ld, i)
+                      : p_entry<T>(b.F, b.in_edge, i0, i1, b.Sout[x], ld, i);
             po = (double)b.P[x];
             b.P[x] = (T)pn;
             y = (double)b.Y[x];
@@ -965,8 +1035,12 @@ __global__ __launch_bounds__(NB) void p_from_f_kernel(Consts c, Bufs<T> b)
     const int j = blockIdx.y;
     const int i = blockIdx.x * NB + threadIdx.x;
     if (i >= c.n) return;
-    T so = T(0);
     const int e0 = b.out_off[j], e1 = b.out_off[j + 1];
+    if (c.edge_par == 2) {  // flat edge phase: the node phase gathers both lists, as here
+        b.P[(long long)j * c.ld + i] = (T)p_entry_flat<T>(b.F, b.in_edge, b.in_off[j], b.in_off[j + 1], e0, e1, c.ld, i);
+        return;
+    }
+    T so = T(0);
     if (c.edge_par) {
         // per wave of the concurrent edge phase (edges e0 + w, e0 + w + NW, ...), then over the waves
         for (int w = 0; w < EDGE_PAR_WAVES; ++w) {
@@ -1587,11 +1661,15 @@ __global__ void pool_gather_kernel(const SlotDesc<T> *slots, int nslots, DevScal
 // lane holds 2 * NV * VEC iterate values (F and q), with the out-edge sums in LDS; 8 waves per
 // column keep that near 100 VGPRs, 16 for the largest FP64 columns.  {1, nv, 1}: edge_kernel_par
 // (one wave per out-edge, columns of up to 64 nv vec entries); {wpe, nv, 0}: edge_kernel with
-// wpe waves per column of up to 64 wpe nv vec entries, the out-edges of a tail in turn.
-static const EdgeShape EDGE_SHAPES_F32[] = {{1, 1, 1}, {1, 2, 1}, {1, 4, 1}, {1, 8, 1}, {4, 1, 0}, {4, 2, 0},
-                                            {4, 4, 0}, {8, 3, 0}, {8, 4, 0}, {8, 6, 0}, {8, 8, 0}};
-static const EdgeShape EDGE_SHAPES_F64[] = {{1, 1, 1}, {1, 2, 1}, {1, 4, 1}, {1, 8, 1}, {4, 1, 0},
-                                            {4, 2, 0}, {4, 4, 0}, {8, 4, 0}, {8, 8, 0}, {16, 8, 0}};
+// wpe waves per column of up to 64 wpe nv vec entries, the out-edges of a tail in turn;
+// {1, nv, 2}: edge_kernel_flat, one wave per edge over a flat grid of edges (columns of up to
+// 64 nv vec entries), the out-edge sums gathered by the node phase.
+static const EdgeShape EDGE_SHAPES_F32[] = {{1, 1, 1}, {1, 2, 1}, {1, 4, 1}, {1, 8, 1}, {1, 1, 2}, {1, 2, 2},
+                                            {1, 4, 2}, {1, 8, 2}, {4, 1, 0}, {4, 2, 0}, {4, 4, 0}, {8, 3, 0},
+                                            {8, 4, 0}, {8, 6, 0}, {8, 8, 0}};
+static const EdgeShape EDGE_SHAPES_F64[] = {{1, 1, 1}, {1, 2, 1}, {1, 4, 1}, {1, 8, 1}, {1, 1, 2}, {1, 2, 2},
+                                            {1, 4, 2}, {1, 8, 2}, {4, 1, 0}, {4, 2, 0}, {4, 4, 0}, {8, 4, 0},
+                                            {8, 8, 0}, {16, 8, 0}};
 
 int edge_shape_list(int bytes, const EdgeShape **list)
 {
@@ -1699,10 +1777,32 @@ static void edge_par_go(const Consts &c, const Bufs<T> &b, const PartLayout &pl,
         MCF_LAUNCH((edge_kernel_par<T, NV, false, false>), grid, block, 0, st, e0, e1, 0, c, b, pl);
 }
 
+template <typename T, int NV>
+static void edge_flat_go(const Consts &c, const Bufs<T> &b, const PartLayout &pl, bool check, bool partial,
+                         hipStream_t st, hipEvent_t e0, hipEvent_t e1)
+{
+    const dim3 grid(xcd_grid(c.nep)), block(64 * EDGE_PAR_WAVES);
+    if (check)
+        MCF_LAUNCH((edge_kernel_flat<T, NV, true, true>), grid, block, 0, st, e0, e1, 0, c, b, pl);
+    else if (partial)
+        MCF_LAUNCH((edge_kernel_flat<T, NV, false, true>), grid, block, 0, st, e0, e1, 0, c, b, pl);
+    else
+        MCF_LAUNCH((edge_kernel_flat<T, NV, false, false>), grid, block, 0, st, e0, e1, 0, c, b, pl);
+}
+
 template <typename T>
 hipError_t launch_edge(const Consts &c, const Bufs<T> &b, const PartLayout &pl, EdgeShape sh, bool check,
                        bool partial, hipStream_t st, hipEvent_t e0, hipEvent_t e1)
 {
+    if (sh.par == 2) {
+        switch (sh.ept) {
+        case 1: edge_flat_go<T, 1>(c, b, pl, check, partial, st, e0, e1); return hipGetLastError();
+        case 2: edge_flat_go<T, 2>(c, b, pl, check, partial, st, e0, e1); return hipGetLastError();
+        case 4: edge_flat_go<T, 4>(c, b, pl, check, partial, st, e0, e1); return hipGetLastError();
+        case 8: edge_flat_go<T, 8>(c, b, pl, check, partial, st, e0, e1); return hipGetLastError();
+        default: return hipErrorInvalidValue;
+        }
+    }
     if (sh.par) {
         switch (sh.ept) {
         case 1: edge_par_go<T, 1>(c, b, pl, check, partial, st, e0, e1); return hipGetLastError();

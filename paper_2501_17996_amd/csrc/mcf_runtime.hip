@@ -652,7 +652,7 @@ int32_t mcf_edge_shapes(int32_t precision, int32_t *waves, int32_t *vectors, int
     const EdgeShape *list;
     const int cnt = edge_shape_list(precision == MCF_FP32 ? 4 : 8, &list);
     for (int x = 0; x < cnt && x < cap; ++x) {
-        if (waves) waves[x] = list[x].par ? 1 : list[x].wpe;
+        if (waves) waves[x] = list[x].par == 2 ? -1 : list[x].par ? 1 : list[x].wpe;
         if (vectors) vectors[x] = list[x].ept;
     }
     return cnt;
@@ -715,7 +715,8 @@ int prepare_solver(int32_t n, int32_t m, const int32_t *tail, const int32_t *hea
     const int bytes = o.precision == MCF_FP32 ? 4 : 8;
     EdgeShape shape = edge_shape_for(n, bytes);
     if (o.edge_waves != 0 || o.edge_vectors != 0) {
-        const EdgeShape want{o.edge_waves, o.edge_vectors, o.edge_waves == 1 ? 1 : 0};
+        const EdgeShape want = o.edge_waves == -1 ? EdgeShape{1, o.edge_vectors, 2}
+                                                  : EdgeShape{o.edge_waves, o.edge_vectors, o.edge_waves == 1 ? 1 : 0};
         if (!edge_shape_valid(want, n, bytes)) return MCF_E_ARG;
         shape = want;
     }
@@ -770,7 +771,8 @@ int prepare_solver(int32_t n, int32_t m, const int32_t *tail, const int32_t *hea
     c.node_latency = o.node_form == 1 ? 1
                      : o.node_form == 2 ? 0
                      : (long long)n * m * (o.precision == MCF_FP32 ? 4 : 8) <= NODE_LATENCY_BYTES ? 1 : 0;
-    c.nep = n;  // edge quantities are added per tail node
+    // edge quantities are added per tail node, or per workgroup of the flat edge phase
+    c.nep = s->sh.par == 2 ? (m + EDGE_PAR_WAVES - 1) / EDGE_PAR_WAVES : n;
     c.nrp = (m + RES_EDGES - 1) / RES_EDGES;
     c.nnp = fused ? n : c.nblk_node;
     *out = s;

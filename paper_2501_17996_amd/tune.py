@@ -40,7 +40,7 @@ WARMUP, TIMED = 20, 63   # sampled iterations k = 21, 28, ..., 77: regular ones 
 
 def covers(waves: int, vectors: int, n: int, precision: int) -> bool:
     vec = 4 if precision == 1 else 2
-    return n <= 64 * waves * vectors * vec
+    return n <= 64 * abs(waves) * vectors * vec   # waves -1: the flat form, one wave per column
 
 
 def time_candidate(mcf, inst, precision, waves, vectors, node_block):
@@ -200,7 +200,9 @@ def write_inc(results, sizes, path=INC):
             rows = results.get((precision, n))
             if rows:
                 ms, waves, vectors, nb = rows[0]
-                entries[(4 if precision else 8, n)] = (waves, vectors, 1 if waves == 1 else 0, nb, ms * 1e3)
+                # waves -1 (flat) is the compiled shape {1, vectors, 2}; 1 (concurrent) is {1, vectors, 1}
+                w, par = (1, 2) if waves == -1 else (waves, 1 if waves == 1 else 0)
+                entries[(4 if precision else 8, n)] = (w, vectors, par, nb, ms * 1e3)
     lines = ["// Two-phase launch shapes by measurement, written by paper_2501_17996_amd/tune.py on one",
              "// MI355X (ring + chords instances of out-degree 10; mean regular-iteration time of the",
              "// edge and node launches).  Entries ascend in n_max per iterate size.",

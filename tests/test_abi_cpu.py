@@ -117,7 +117,14 @@ def test_forced_launch_shapes_are_validated(mcf):
         mcf.mcf_create(big.n, big.tail, big.head, big.cap, big.utility, big.gamma, big.w,
                        opt(edge_waves=1, edge_vectors=2))
     assert ei.value.code == E
+    with pytest.raises(mcf.MCFError) as ei:                     # the flat form has one wave per column too
+        mcf.mcf_create(big.n, big.tail, big.head, big.cap, big.utility, big.gamma, big.w,
+                       opt(edge_waves=-1, edge_vectors=2))
+    assert ei.value.code == E
+    _expect(mcf, E, opt=opt(edge_waves=-1, edge_vectors=3))    # not a compiled flat shape
     assert (8, 3) in mcf.mcf_edge_shapes(1) and (8, 3) not in mcf.mcf_edge_shapes(0)
+    for precision in (0, 1):
+        assert {(-1, v) for v in (1, 2, 4, 8)} <= set(mcf.mcf_edge_shapes(precision))
     assert mcf.mcf_edge_shapes(7) == []
 
 
@@ -133,8 +140,11 @@ def test_tuned_table_is_well_formed(mcf):
             continue   # sentinel
         precision = 1 if b == 4 else 0
         assert b in (4, 8) and nb in (64, 256)
-        assert par == (1 if waves == 1 else 0)
-        assert (waves, vectors) in mcf.mcf_edge_shapes(precision)
+        if par == 2:   # the flat edge phase: one wave per edge, listed as waves -1
+            assert waves == 1 and (-1, vectors) in mcf.mcf_edge_shapes(precision)
+        else:
+            assert par == (1 if waves == 1 else 0)
+            assert (waves, vectors) in mcf.mcf_edge_shapes(precision)
         assert n_max <= 64 * waves * vectors * (16 // b)
         assert n_max > last.get(b, 0)
         last[b] = n_max

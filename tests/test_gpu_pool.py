@@ -401,13 +401,15 @@ def test_pool_graph_cache_eviction(M):
 
 
 def test_slow_instance_in_the_pool_tracks_the_oracle(M):
-    """The ring of 400 nodes with out-degree 4 (log utility, seed 44) converges slowly: its dual
-    residual is the last to close, and the oracle itself is still near rel_kkt 3e-3 at iteration
-    9000 with omega adapted throughout (about 1e-4 with omega frozen at 1000).  An earlier pool
-    test that required every instance to converge within its iteration limit failed on it.
-    Here the FP64 pool and the oracle agree on its first 1000 iterations (state to 1e-10, omega,
-    and rel_kkt), and both are still far from the tolerance there: the slow convergence is the
-    method's on this instance, not the pool's."""
+    """The ring of 400 nodes with out-degree 4 (log utility, seed 44) does not reach rel_kkt 1e-4
+    with omega adapted throughout: in the FP64 oracle omega rises to about 9500, falls back near
+    300 (rel_kkt 3e-3 at iteration 9000), then drifts down to 9e-5 by iteration 65000 while the
+    dual residual stays at rel_kkt 0.024 -- the drift of the adaptive primal weight seen on the
+    paper's kNN instances.  With omega frozen from iteration 1000 (Section 2.4) the oracle
+    converges at iteration 13000.  An earlier pool test that required every instance of its mix
+    to converge within 60000 iterations failed on this one.  Here the FP64 pool and the oracle
+    agree on its first 1000 iterations (state to 1e-10, omega, rel_kkt), both still far from the
+    tolerance: the behaviour is the method's on this instance, not the pool's."""
     inst = I.ring_instance(400, 4, seed=44, utility=0, gamma=0.5)
     pool = M.Pool(0, max_slots=1, check_every=K)
     h = M.Solver(inst, precision=0, tol=1e-4, check_every=K, max_iter=60000)
