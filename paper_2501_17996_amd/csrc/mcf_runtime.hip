@@ -767,12 +767,13 @@ int prepare_solver(int32_t n, int32_t m, const int32_t *tail, const int32_t *hea
     c.nblk_node = node_blocks(n, node_block);
     c.node_block = node_block;
     c.fused = fused ? 1 : 0;
-    c.edge_par = s->sh.par;
+    c.edge_par = fused ? 0 : s->sh.par;  // the edge shape is the two-phase iteration's
     c.node_latency = o.node_form == 1 ? 1
                      : o.node_form == 2 ? 0
                      : (long long)n * m * (o.precision == MCF_FP32 ? 4 : 8) <= NODE_LATENCY_BYTES ? 1 : 0;
-    // edge quantities are added per tail node, or per workgroup of the flat edge phase
-    c.nep = s->sh.par == 2 ? (m + EDGE_PAR_WAVES - 1) / EDGE_PAR_WAVES : n;
+    // edge quantities are added per tail node (per node in the fused iteration), or per workgroup of
+    // the flat edge phase
+    c.nep = c.edge_par == 2 ? (m + EDGE_PAR_WAVES - 1) / EDGE_PAR_WAVES : n;
     c.nrp = (m + RES_EDGES - 1) / RES_EDGES;
     c.nnp = fused ? n : c.nblk_node;
     *out = s;
