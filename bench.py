@@ -165,7 +165,8 @@ def pool_leg(mcf, torch, slots: int, steps: int, K: int):
     stream = torch.cuda.Stream()     # a stream of its own (default priority): the events bracket its work
     insts = [I.serving_request(r) for r in range(slots)]
     pool = mcf.Pool(mcf.MCF_FP32, 0, slots, K, stream=stream.cuda_stream)
-    hs = [mcf.Solver(i, precision=mcf.MCF_FP32, tol=1e-14, check_every=K, max_iter=10 ** 8) for i in insts]
+    # each instance in the organisation the pool runs fastest for its size
+    hs = [mcf.Solver(i, tol=1e-14, check_every=K, max_iter=10 ** 8, **pool.instance_options(i.n)) for i in insts]
     for h in hs:
         pool.admit(h)
     for _ in range(3):
@@ -183,6 +184,7 @@ def pool_leg(mcf, torch, slots: int, steps: int, K: int):
     wall = time.perf_counter() - t0
     ev_ms = e0.elapsed_time(e1)
     shape = pool.shape()
+    two_phase = sum(h.layout()["kernel_mode"] == "two_phase" for h in hs)
     pool.close()
     for h in hs:
         h.close()
@@ -192,6 +194,7 @@ def pool_leg(mcf, torch, slots: int, steps: int, K: int):
     upd = sum(i.n * i.m for i in insts)
     return {"workload": f"{slots} requests of the serving stream in one pool, FP32, steps of {K} iterations",
             "n_total": sum(i.n for i in insts), "nm_total": upd, "shape": shape,
+            "two_phase_instances": two_phase,
             "us_per_iteration": per_it * 1e6, "edge_dest_updates_per_s": upd / per_it,
             "wall_updates_per_s": upd * steps * K / wall,
             "roofline": {"bound": "hbm", "achieved": alg / per_it / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",

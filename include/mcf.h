@@ -229,9 +229,10 @@ int mcf_layout(const mcf_solver *s, int32_t *ld, int32_t *edge_block, int32_t *e
 
 /* ---------------------------------------------------------------- batching pool
  * A pool runs many instances (each created with n <= 512 and the pool's precision) in one
- * stream: every pool iteration is one launch that performs one PDHG iteration of every active
- * instance, whatever its size or utility, followed on check iterations by one residual and one
- * control launch for all of them.  Each instance follows its own Algorithm 2.1 (its own
+ * stream: every pool iteration performs one PDHG iteration of every active instance, whatever
+ * its size or utility: one launch for the instances in the fused iteration, and one edge and
+ * one node launch for those in the two-phase iteration, followed on check iterations by one
+ * residual and one control launch for all of them.  Each instance follows its own Algorithm 2.1 (its own
  * iteration count, primal weight, adapt schedule and stop test); the residual of every
  * instance is evaluated at the last iteration of each mcf_pool_step.  Instances are admitted
  * and retired between steps (continuous batching); a converged instance stops iterating at
@@ -253,7 +254,7 @@ typedef struct {
     int32_t max_slots;      /* 1 .. MCF_POOL_MAX_SLOTS */
     int32_t check_every;    /* default step length for callers */
     int32_t n_max;          /* largest n admitted, 2 .. 512 (0: 512); it sets the launch shape */
-    /* Waves per node workgroup: 8 or (FP32 only) 4; 0 = the measured choice for n_max and the
+    /* Waves per node workgroup: 8 or (FP32 only) 4, 2 or 1; 0 = the measured choice for n_max and the
      * precision (the table tune.py writes).  Results depend on it only through the order of
      * floating-point sums, and never on which other instances share the pool. */
     int32_t waves;
@@ -273,9 +274,18 @@ int mcf_pool_create(const mcf_pool_options *opt, mcf_pool **out);
  * 2, 4 or 8). */
 int mcf_pool_shape(const mcf_pool *p, int32_t *waves, int32_t *grid, int32_t *max_ept);
 
+/* Sets in *o the precision, kernel organisation and launch shape that an instance of n nodes
+ * should be created with to run in this pool: the organisation `tune.py --pool` measured faster
+ * in a saturated pool for that size (the fused iteration, or the two-phase one with the flat
+ * edge phase and 64-thread node blocks).  Other fields are left as they are.  MCF_E_ARG if n is
+ * outside 2 .. n_max. */
+int mcf_pool_instance_options(const mcf_pool *p, int32_t n, mcf_options *o);
+
 /* Admits a solver into a free slot.  MCF_E_NOMEM when no slot is free or the budget would be
  * exceeded (retry after a retire); MCF_E_ARG when the solver is already pooled, has another
- * precision, uses the two-phase iteration or has more than n_max nodes; MCF_E_STATE when it
+ * precision, has more than n_max nodes, or uses the two-phase iteration in another form than
+ * the flat edge phase with at most 4 vectors per lane and 64-thread node blocks (the form
+ * mcf_pool_instance_options gives); MCF_E_STATE when it
  * has converged or diverged.  The solver keeps its state and continues from its current
  * iteration. */
 int mcf_pool_admit(mcf_pool *p, mcf_solver *s, int32_t *slot);

@@ -38,6 +38,7 @@ struct Consts {
                            // (out-edge sums gathered by the node phase)
     int node_latency;      // 1: regular node launches in the latency form (F within NODE_LATENCY_BYTES)
     int nrp;               // partials of the residual pass (a, b; one per RES_EDGES edges)
+    int edge_ept;          // 16-byte vectors per lane of the two-phase edge shape
 };
 
 // Algorithm 2.1 step 3 adapts omega at iterations k that are multiples of k_adapt (k = 0
@@ -160,20 +161,27 @@ struct SlotDesc {
 // captured graph; the last launch of each step advances G.
 struct PoolState {
     long long G;
-    int nwork;  // node items (slot, node) of the batched iteration
+    int nwork;  // fused node items (slot, node) of the batched iteration
     int nres;   // residual items (slot, block of RES_EDGES edges)
+    int nedge;  // flat edge items of the two-phase slots (slot, block of EDGE_PAR_WAVES edges)
+    int nnode;  // node items of the two-phase slots (slot, node j * ceil(n/64) + row block)
 };
 
-// Launch shape of a pool: waves per node workgroup (4 or 8), the grids of the iteration and
+// Waves (one node item each) per workgroup of the pool's two-phase node launch.
+constexpr int POOL_NODE_WAVES = 4;
+
+// Launch shape of a pool: waves per node workgroup (1, 2, 4 or 8), the grids of the iteration and
 // residual launches (the item counts rounded up; set per step), and the largest entries per lane
 // of an admitted instance (1, 2, 4 or 8: n <= 64 ept).
 struct PoolShape {
     int waves, grid, res_grid, max_ept;
+    int edge_grid, node_grid;  // grids of the two-phase slots' edge and node launches (0: none)
 };
 
 template <typename T>
-hipError_t launch_pool_iteration(const SlotDesc<T> *slots, const int2 *work, const int *res_off, const PoolState *ps,
-                                 int nslots, PoolShape sh, int it, bool check, bool control, hipStream_t st);
+hipError_t launch_pool_iteration(const SlotDesc<T> *slots, const int2 *work, const int2 *ework, const int2 *nwork,
+                                 const int *res_off, const PoolState *ps, int nslots, PoolShape sh, int it, bool check,
+                                 bool control, hipStream_t st);
 template <typename T>
 hipError_t launch_pool_gather(const SlotDesc<T> *slots, int nslots, DevScalars *out, PoolState *ps, int iters,
                               hipStream_t st);
@@ -181,5 +189,8 @@ hipError_t launch_pool_gather(const SlotDesc<T> *slots, int nslots, DevScalars *
 // size `bytes` whose instances have at most n_max nodes
 bool pool_waves_valid(int waves, int bytes);
 PoolShape pool_shape_for(int n_max, int bytes);
+// the organisation measured fastest in a saturated pool for an instance of n nodes: 0 = fused,
+// 1 = two-phase (flat edge phase, 64-thread node blocks)
+int pool_org_for(int n, int bytes);
 
 }  // namespace mcf

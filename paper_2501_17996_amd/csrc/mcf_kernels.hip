@@ -828,14 +828,14 @@ void edge_kernel_par(Consts c, Bufs<T> b, PartLayout pl)
 // and no tail's out-edges form a second round.  The out-edge sums are left to the node phase,
 // which gathers the out-edges of F as well as the in-edges.  Partials per workgroup: wave
 // totals added in wave order.
+// Workgroup `blk` of the flat edge phase (EDGE_PAR_WAVES waves, edges blk NW + wave); the wave
+// totals of its partials are added in wave order through `red` (3 NW doubles).  Every wave of
+// the workgroup calls it with the same blk.
 template <typename T, int NV, bool CHECK, bool PARTIAL>
-__global__ __launch_bounds__(64 * EDGE_PAR_WAVES) void edge_kernel_flat(Consts c, Bufs<T> b, PartLayout pl)
+__device__ __forceinline__ void flat_block(const Consts &c, const Bufs<T> &b, const PartLayout &pl, int blk,
+                                           double *red)
 {
     constexpr int NW = EDGE_PAR_WAVES;
-    __shared__ double red[3 * NW];
-    if (b.sc->stop) return;
-    const int blk = xcd_item(blockIdx.x, c.nep);
-    if (blk >= c.nep) return;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), t = threadIdx.x & 63;
     const int e = blk * NW + w;
     double dF_w = 0.0, e_w = 0.0, sup_w = 0.0;
@@ -864,6 +864,16 @@ __global__ __launch_bounds__(64 * EDGE_PAR_WAVES) void edge_kernel_flat(Consts c
             b.part[pl.sup + blk] = cc;
         }
     }
+}
+
+template <typename T, int NV, bool CHECK, bool PARTIAL>
+__global__ __launch_bounds__(64 * EDGE_PAR_WAVES) void edge_kernel_flat(Consts c, Bufs<T> b, PartLayout pl)
+{
+    __shared__ double red[3 * EDGE_PAR_WAVES];
+    if (b.sc->stop) return;
+    const int blk = xcd_item(blockIdx.x, c.nep);
+    if (blk >= c.nep) return;
+    flat_block<T, NV, CHECK, PARTIAL>(c, b, pl, blk, red);
 }
 
 // -------------------------------------------------------------- node phase
@@ -936,15 +946,17 @@ __device__ __forceinline__ double p_entry_flat(const T *X, const int *in_edge, i
 }
 
 // LAT: the latency form (regular launches of instances whose F is within NODE_LATENCY_BYTES).
+// Block (row block xb, node column j) of the node phase, run by NB threads: thread t owns entry
+// i = xb NB + t of column j; `blk` is the block's partial index (j nxb + xb).  For NB = 64 the
+// block is one wave and its sums need no barrier (the batching pool runs several such blocks of
+// different instances in one workgroup).  `lds` holds 2 NB/64 doubles private to the block.
 template <typename T, int NB, int UTIL, bool CHECK, bool PARTIAL, bool LAT>
-__global__ __launch_bounds__(NB) void node_kernel(Consts c, Bufs<T> b, PartLayout pl)
+__device__ __forceinline__ void node_body(const Consts &c, const Bufs<T> &b, const PartLayout &pl, int j, int xb,
+                                          int blk, double *lds)
 {
     constexpr int NW = NB / 64;
-    __shared__ double lds[2 * NW];
-    if (b.sc->stop) return;
-    const int j = blockIdx.y;
-    const int i = blockIdx.x * NB + threadIdx.x;
-    const int blk = blockIdx.y * gridDim.x + blockIdx.x;
+    const int tid = threadIdx.x & (NB - 1);
+    const int i = xb * NB + tid;
     const long long ld = c.ld;
     const double beta = b.sc->beta, g = c.gamma;
     double dy2 = 0.0, p = 0.0, conj = 0.0, rnum = 0.0, rden = 0.0, nonpos = 0.0, yinf = 0.0;
@@ -1014,7 +1026,7 @@ __global__ __launch_bounds__(NB) void node_kernel(Consts c, Bufs<T> b, PartLayou
         group_sum<NW>(rnum, rden, lds);
         group_sum<NW>(nonpos, yinf, lds);
     }
-    if (threadIdx.x == 0) {
+    if (tid == 0) {
         if (PARTIAL) b.part[pl.dY + blk] = dy2;
         if (CHECK) {
             b.part[pl.p + blk] = p;
@@ -1025,6 +1037,15 @@ __global__ __launch_bounds__(NB) void node_kernel(Consts c, Bufs<T> b, PartLayou
             b.part[pl.yinf + blk] = yinf;
         }
     }
+}
+
+template <typename T, int NB, int UTIL, bool CHECK, bool PARTIAL, bool LAT>
+__global__ __launch_bounds__(NB) void node_kernel(Consts c, Bufs<T> b, PartLayout pl)
+{
+    __shared__ double lds[2 * (NB / 64)];
+    if (b.sc->stop) return;
+    node_body<T, NB, UTIL, CHECK, PARTIAL, LAT>(c, b, pl, blockIdx.y, blockIdx.x, blockIdx.y * gridDim.x + blockIdx.x,
+                                                lds);
 }
 
 // P = F A^T of the current F, with the out-edge sums formed in the iterate type and in the
@@ -1600,6 +1621,63 @@ __global__ __launch_bounds__(64 * NWV) void pool_fused_kernel(const SlotDesc<T> 
     else pool_util<T, 8, CHECK, NWV>(d, parity, wk.y, partial, vsh, red, incs);
 }
 
+// Two-phase slots of the pool.  Edge launch: workgroup b is flat edge item b = (slot, block of
+// EDGE_PAR_WAVES edges), one wave per edge (the flat edge phase of a single solve).
+template <typename T, int NV, bool CHECK>
+__device__ __forceinline__ void pool_flat(const SlotDesc<T> &d, int blk, bool partial, double *red)
+{
+    if (CHECK) flat_block<T, NV, true, true>(d.c, d.b, d.pl, blk, red);
+    else if (partial) flat_block<T, NV, false, true>(d.c, d.b, d.pl, blk, red);
+    else flat_block<T, NV, false, false>(d.c, d.b, d.pl, blk, red);
+}
+
+template <typename T, bool CHECK>
+__global__ __launch_bounds__(64 * EDGE_PAR_WAVES) void pool_edge_kernel(const SlotDesc<T> *slots, const int2 *ework,
+                                                                        const PoolState *ps, int it)
+{
+    __shared__ double red[3 * EDGE_PAR_WAVES];
+    if ((int)blockIdx.x >= ps->nedge) return;
+    const int2 wk = ework[blockIdx.x];
+    const SlotDesc<T> &d = slots[wk.x];
+    long long k;
+    if (!slot_live(d, ps->G + it, k)) return;
+    const bool partial = CHECK || adapts_at(d.c, k);
+    if (d.c.edge_ept == 1) pool_flat<T, 1, CHECK>(d, wk.y, partial, red);
+    else if (d.c.edge_ept == 2) pool_flat<T, 2, CHECK>(d, wk.y, partial, red);
+    else pool_flat<T, 4, CHECK>(d, wk.y, partial, red);
+}
+
+// Node launch: each wave of a workgroup is node item (slot, j * ceil(n/64) + xb): rows
+// 64 xb .. 64 xb + 63 of column j, the node phase of a single solve with 64-thread blocks (wave
+// sums only, no barrier), in its latency form, which computes the same values as the streaming
+// form.  Waves past the item count return at once.
+template <typename T, int UTIL, bool CHECK>
+__device__ __forceinline__ void pool_node_util(const SlotDesc<T> &d, int j, int xb, int blk, bool partial)
+{
+    if (CHECK) node_body<T, 64, UTIL, true, true, false>(d.c, d.b, d.pl, j, xb, blk, nullptr);
+    else if (partial) node_body<T, 64, UTIL, false, true, false>(d.c, d.b, d.pl, j, xb, blk, nullptr);
+    else node_body<T, 64, UTIL, false, false, true>(d.c, d.b, d.pl, j, xb, blk, nullptr);
+}
+
+template <typename T, bool CHECK>
+__global__ __launch_bounds__(64 * POOL_NODE_WAVES) void pool_node_kernel(const SlotDesc<T> *slots, const int2 *nwork,
+                                                                         const PoolState *ps, int it)
+{
+    const int item = (int)blockIdx.x * POOL_NODE_WAVES + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (item >= ps->nnode) return;
+    const int2 wk = nwork[item];
+    const SlotDesc<T> &d = slots[wk.x];
+    long long k;
+    if (!slot_live(d, ps->G + it, k)) return;
+    const bool partial = CHECK || adapts_at(d.c, k);
+    const int nxb = (d.c.n + 63) / 64;
+    const int j = wk.y / nxb, xb = wk.y - j * nxb;
+    if (d.c.utility == 0) pool_node_util<T, 0, CHECK>(d, j, xb, wk.y, partial);
+    else if (d.c.utility == 1 && d.c.c1 == 1.0) pool_node_util<T, UTIL_POWER_HALF, CHECK>(d, j, xb, wk.y, partial);
+    else if (d.c.utility == 1) pool_node_util<T, 1, CHECK>(d, j, xb, wk.y, partial);
+    else pool_node_util<T, 2, CHECK>(d, j, xb, wk.y, partial);
+}
+
 // Residual pass of every slot: workgroup b is block b - res_off[s] of slot s, where res_off
 // (nslots + 1 entries, nondecreasing) counts the residual blocks of the slots before s.
 template <typename T>
@@ -1928,17 +2006,27 @@ hipError_t launch_poison(const Bufs<T> &b, int which, long long offset, hipStrea
 }
 
 // Pool shapes compiled per iterate size: waves per node workgroup.
-bool pool_waves_valid(int waves, int bytes) { return waves == 8 || (bytes == 4 && waves == 4); }
+bool pool_waves_valid(int waves, int bytes)
+{
+    return waves == 8 || (bytes == 4 && (waves == 4 || waves == 2 || waves == 1));
+}
 
 // Measured pool shapes (written by tune.py), by the largest n a pool admits.
 struct TunedPool {
-    int bytes, n_max, waves;
+    int bytes, n_max, waves, org;
 };
 #include "tuned_pool.inc"
 
+int pool_org_for(int n, int bytes)
+{
+    for (const TunedPool &t : TUNED_POOL)
+        if (t.bytes == bytes && n <= t.n_max) return t.org == 1 ? 1 : 0;
+    return 0;
+}
+
 PoolShape pool_shape_for(int n_max, int bytes)
 {
-    PoolShape sh{8, 0, 0, n_max <= 64 ? 1 : n_max <= 128 ? 2 : n_max <= 256 ? 4 : 8};
+    PoolShape sh{8, 0, 0, n_max <= 64 ? 1 : n_max <= 128 ? 2 : n_max <= 256 ? 4 : 8, 0, 0};
     for (const TunedPool &t : TUNED_POOL)
         if (t.bytes == bytes && n_max <= t.n_max) {
             if (pool_waves_valid(t.waves, bytes)) sh.waves = t.waves;
@@ -1962,12 +2050,35 @@ static void pool_fused_go(const SlotDesc<T> *slots, const int2 *work, const Pool
 
 // sh.grid and sh.res_grid bound the item counts the pool state holds
 template <typename T>
-hipError_t launch_pool_iteration(const SlotDesc<T> *slots, const int2 *work, const int *res_off, const PoolState *ps,
-                                 int nslots, PoolShape sh, int it, bool check, bool control, hipStream_t st)
+hipError_t launch_pool_iteration(const SlotDesc<T> *slots, const int2 *work, const int2 *ework, const int2 *nwork,
+                                 const int *res_off, const PoolState *ps, int nslots, PoolShape sh, int it, bool check,
+                                 bool control, hipStream_t st)
 {
-    if (sh.grid < 1 || !pool_waves_valid(sh.waves, sizeof(T))) return hipErrorInvalidValue;
-    if (sh.waves == 8) pool_fused_go<T, 8>(slots, work, ps, sh, it, check, st);
-    else if constexpr (sizeof(T) == 4) pool_fused_go<T, 4>(slots, work, ps, sh, it, check, st);
+    if (!pool_waves_valid(sh.waves, sizeof(T))) return hipErrorInvalidValue;
+    if (sh.edge_grid > 0) {  // two-phase slots: edge items (independent of the fused items)
+        if (check)
+            hipLaunchKernelGGL((pool_edge_kernel<T, true>), dim3(sh.edge_grid), dim3(64 * EDGE_PAR_WAVES), 0, st,
+                               slots, ework, ps, it);
+        else
+            hipLaunchKernelGGL((pool_edge_kernel<T, false>), dim3(sh.edge_grid), dim3(64 * EDGE_PAR_WAVES), 0, st,
+                               slots, ework, ps, it);
+    }
+    if (sh.grid < 1) {
+        // no fused slots
+    } else if (sh.waves == 8) pool_fused_go<T, 8>(slots, work, ps, sh, it, check, st);
+    else if constexpr (sizeof(T) == 4) {
+        if (sh.waves == 4) pool_fused_go<T, 4>(slots, work, ps, sh, it, check, st);
+        else if (sh.waves == 2) pool_fused_go<T, 2>(slots, work, ps, sh, it, check, st);
+        else pool_fused_go<T, 1>(slots, work, ps, sh, it, check, st);
+    }
+    if (sh.node_grid > 0) {  // two-phase slots: node items, after their edge items
+        if (check)
+            hipLaunchKernelGGL((pool_node_kernel<T, true>), dim3(sh.node_grid), dim3(64 * POOL_NODE_WAVES), 0, st,
+                               slots, nwork, ps, it);
+        else
+            hipLaunchKernelGGL((pool_node_kernel<T, false>), dim3(sh.node_grid), dim3(64 * POOL_NODE_WAVES), 0, st,
+                               slots, nwork, ps, it);
+    }
     if (check && sh.res_grid > 0)
         hipLaunchKernelGGL(pool_residual_kernel<T>, dim3(sh.res_grid), dim3(64 * RES_EDGES), 0, st, slots, res_off, ps,
                            nslots, it);
@@ -1999,8 +2110,9 @@ hipError_t launch_pool_gather(const SlotDesc<T> *slots, int nslots, DevScalars *
                                           long long, hipStream_t);                                              \
     template hipError_t launch_poison<T>(const Bufs<T> &, int, long long, hipStream_t);                      \
     template hipError_t launch_p_from_f<T>(const Consts &, const Bufs<T> &, hipStream_t);                    \
-    template hipError_t launch_pool_iteration<T>(const SlotDesc<T> *, const int2 *, const int *, const PoolState *, \
-                                                 int, PoolShape, int, bool, bool, hipStream_t);               \
+    template hipError_t launch_pool_iteration<T>(const SlotDesc<T> *, const int2 *, const int2 *, const int2 *,     \
+                                                 const int *, const PoolState *, int, PoolShape, int, bool, bool, \
+                                                 hipStream_t);                                                \
     template hipError_t launch_pool_gather<T>(const SlotDesc<T> *, int, DevScalars *, PoolState *, int, hipStream_t);
 
 MCF_INSTANTIATE(float)

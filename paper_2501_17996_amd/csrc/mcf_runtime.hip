@@ -775,6 +775,7 @@ int prepare_solver(int32_t n, int32_t m, const int32_t *tail, const int32_t *hea
     // the flat edge phase
     c.nep = c.edge_par == 2 ? (m + EDGE_PAR_WAVES - 1) / EDGE_PAR_WAVES : n;
     c.nrp = (m + RES_EDGES - 1) / RES_EDGES;
+    c.edge_ept = s->sh.ept;
     c.nnp = fused ? n : c.nblk_node;
     *out = s;
     return MCF_OK;
@@ -1159,6 +1160,9 @@ struct mcf_pool {
     std::vector<SlotDesc<double>> desc;  // host copy (the layout does not depend on the iterate type)
     SlotDesc<double> *d_desc = nullptr;
     int2 *d_work = nullptr;
+    int2 *d_ework = nullptr, *h_ework = nullptr;  // flat edge items of two-phase slots (device, pinned staging)
+    size_t ework_cap = 0;
+    int2 *d_nwork = nullptr, *h_nwork = nullptr;  // node items of two-phase slots
     int *d_res_off = nullptr;
     PoolState *d_state = nullptr;
     DevScalars *d_snap = nullptr;
@@ -1203,21 +1207,48 @@ int pool_upload(mcf_pool *p)
         if (p->desc[sl].active) order.push_back(sl);
     std::stable_sort(order.begin(), order.end(),
                      [&](int a, int b) { return p->desc[a].c.n > p->desc[b].c.n; });
-    int nw = 0, nres = 0;
+    int nw = 0, nres = 0, ne = 0, nn = 0;
+    size_t ne_need = 0;
     for (int sl : order)
-        for (int j = 0; j < p->desc[sl].c.n; ++j) p->h_work[nw++] = make_int2(sl, j);
+        if (!p->desc[sl].c.fused) ne_need += p->desc[sl].c.nep;
+    if (ne_need > p->ework_cap) {  // grow the edge-item lists (the stream is idle)
+        const size_t cap = std::max(ne_need, 2 * p->ework_cap);
+        if (p->d_ework) (void)hipFree(p->d_ework);
+        if (p->h_ework) (void)hipHostFree(p->h_ework);
+        p->d_ework = nullptr;
+        p->h_ework = nullptr;
+        p->ework_cap = 0;
+        MCF_TRY(hipMalloc((void **)&p->d_ework, sizeof(int2) * cap));
+        MCF_TRY(hipHostMalloc((void **)&p->h_ework, sizeof(int2) * cap, hipHostMallocDefault));
+        p->ework_cap = cap;
+    }
+    for (int sl : order) {
+        const Consts &c = p->desc[sl].c;
+        if (c.fused) {
+            for (int j = 0; j < c.n; ++j) p->h_work[nw++] = make_int2(sl, j);
+        } else {
+            for (int blk = 0; blk < c.nep; ++blk) p->h_ework[ne++] = make_int2(sl, blk);
+            for (int x = 0; x < c.nblk_node; ++x) p->h_nwork[nn++] = make_int2(sl, x);
+        }
+    }
     for (int sl = 0; sl < p->max_slots; ++sl) {
         p->h_res_off[sl] = nres;
         if (p->desc[sl].active) nres += p->desc[sl].c.nrp;
     }
     p->h_res_off[p->max_slots] = nres;
-    p->nwork = nw;
+    p->nwork = nw + ne;
     p->shape.grid = pool_grid(nw);
     p->shape.res_grid = pool_grid(nres);
+    p->shape.edge_grid = pool_grid(ne);
+    p->shape.node_grid = pool_grid((nn + POOL_NODE_WAVES - 1) / POOL_NODE_WAVES);
     p->h_state->G = p->G;
     p->h_state->nwork = nw;
     p->h_state->nres = nres;
+    p->h_state->nedge = ne;
+    p->h_state->nnode = nn;
     if (nw) MCF_TRY(hipMemcpyAsync(p->d_work, p->h_work, sizeof(int2) * nw, hipMemcpyHostToDevice, p->stream));
+    if (ne) MCF_TRY(hipMemcpyAsync(p->d_ework, p->h_ework, sizeof(int2) * ne, hipMemcpyHostToDevice, p->stream));
+    if (nn) MCF_TRY(hipMemcpyAsync(p->d_nwork, p->h_nwork, sizeof(int2) * nn, hipMemcpyHostToDevice, p->stream));
     MCF_TRY(hipMemcpyAsync(p->d_res_off, p->h_res_off, sizeof(int) * (p->max_slots + 1), hipMemcpyHostToDevice,
                            p->stream));
     MCF_TRY(hipMemcpyAsync(p->d_state, p->h_state, sizeof(PoolState), hipMemcpyHostToDevice, p->stream));
@@ -1271,8 +1302,8 @@ int pool_enqueue(mcf_pool *p, int iters, const std::vector<int> &adapt_at)
         const bool check = it == iters - 1;
         const bool adapt = a < adapt_at.size() && adapt_at[a] == it;
         if (adapt) ++a;
-        MCF_TRY(launch_pool_iteration<T>(slots, p->d_work, p->d_res_off, p->d_state, p->max_slots, p->shape, it, check,
-                                         check || adapt, p->stream));
+        MCF_TRY(launch_pool_iteration<T>(slots, p->d_work, p->d_ework, p->d_nwork, p->d_res_off, p->d_state,
+                                         p->max_slots, p->shape, it, check, check || adapt, p->stream));
     }
     MCF_TRY(launch_pool_gather<T>(slots, p->max_slots, p->d_snap, p->d_state, iters, p->stream));
     return MCF_OK;
@@ -1290,7 +1321,8 @@ int pool_enqueue_step(mcf_pool *p, int iters)
     const std::vector<int> adapt_at = pool_adapt_points(p, iters);
     if (!p->graphs) return pool_enqueue_any(p, iters, adapt_at);
     std::string key = std::to_string(iters) + "g" + std::to_string(p->shape.grid) + "r" +
-                      std::to_string(p->shape.res_grid);
+                      std::to_string(p->shape.res_grid) + "e" + std::to_string(p->shape.edge_grid) + "n" +
+                      std::to_string(p->shape.node_grid);
     for (int it : adapt_at) key += "," + std::to_string(it);
     auto g = p->graphs_cache.find(key);
     if (g == p->graphs_cache.end()) {
@@ -1370,8 +1402,11 @@ int mcf_pool_create(const mcf_pool_options *opt, mcf_pool **out)
         else rc = MCF_E_DEVICE;
     }
     const size_t work_cap = (size_t)o.max_slots * FUSED_MAX_N;
+    // node items of a two-phase slot: n columns of ceil(n/64) row blocks
+    const size_t nwork_cap = (size_t)o.max_slots * FUSED_MAX_N * ((FUSED_MAX_N + 63) / 64);
     if (!rc && (hipMalloc((void **)&p->d_desc, sizeof(SlotDesc<double>) * o.max_slots) != hipSuccess ||
                 hipMalloc((void **)&p->d_work, sizeof(int2) * work_cap) != hipSuccess ||
+                hipMalloc((void **)&p->d_nwork, sizeof(int2) * nwork_cap) != hipSuccess ||
                 hipMalloc((void **)&p->d_res_off, sizeof(int) * (o.max_slots + 1)) != hipSuccess ||
                 hipMalloc((void **)&p->d_state, sizeof(PoolState)) != hipSuccess ||
                 hipMalloc((void **)&p->d_snap, sizeof(DevScalars) * o.max_slots) != hipSuccess))
@@ -1380,6 +1415,7 @@ int mcf_pool_create(const mcf_pool_options *opt, mcf_pool **out)
                 hipHostMalloc((void **)&p->h_desc, sizeof(SlotDesc<double>) * o.max_slots, hipHostMallocDefault) !=
                     hipSuccess ||
                 hipHostMalloc((void **)&p->h_work, sizeof(int2) * work_cap, hipHostMallocDefault) != hipSuccess ||
+                hipHostMalloc((void **)&p->h_nwork, sizeof(int2) * nwork_cap, hipHostMallocDefault) != hipSuccess ||
                 hipHostMalloc((void **)&p->h_res_off, sizeof(int) * (o.max_slots + 1), hipHostMallocDefault) !=
                     hipSuccess ||
                 hipHostMalloc((void **)&p->h_state, sizeof(PoolState), hipHostMallocDefault) != hipSuccess))
@@ -1408,6 +1444,10 @@ void mcf_pool_destroy(mcf_pool *p)
     if (p->done) (void)hipEventDestroy(p->done);
     if (p->d_desc) (void)hipFree(p->d_desc);
     if (p->d_work) (void)hipFree(p->d_work);
+    if (p->d_ework) (void)hipFree(p->d_ework);
+    if (p->d_nwork) (void)hipFree(p->d_nwork);
+    if (p->h_ework) (void)hipHostFree(p->h_ework);
+    if (p->h_nwork) (void)hipHostFree(p->h_nwork);
     if (p->d_res_off) (void)hipFree(p->d_res_off);
     if (p->d_state) (void)hipFree(p->d_state);
     if (p->d_snap) (void)hipFree(p->d_snap);
@@ -1424,7 +1464,10 @@ int mcf_pool_admit(mcf_pool *p, mcf_solver *s, int32_t *slot)
 {
     if (!p || !s) return MCF_E_ARG;
     if (int rc_ = idle(s)) return rc_;
-    if (s->pool || s->precision != p->precision || !s->c.fused || s->n > p->n_max) return MCF_E_ARG;
+    if (s->pool || s->precision != p->precision || s->n > p->n_max) return MCF_E_ARG;
+    // a two-phase instance must take the flat edge phase (at most 4 vectors per lane) and 64-thread
+    // node blocks, the forms the pool's launches run (mcf_pool_instance_options gives them)
+    if (!s->c.fused && (s->c.edge_par != 2 || s->c.edge_ept > 4 || s->c.node_block != 64)) return MCF_E_ARG;
     if (s->state == MCF_CONVERGED || s->state == MCF_DIVERGED) return MCF_E_STATE;
     int rc = mcf_pool_sync(p);
     if (rc) return rc;
@@ -1505,6 +1548,24 @@ int mcf_pool_retire(mcf_pool *p, int32_t slot)
     s->pool = nullptr;
     s->pool_slot = -1;
     return pool_upload(p);
+}
+
+int mcf_pool_instance_options(const mcf_pool *p, int32_t n, mcf_options *o)
+{
+    if (!p || !o || n < 2 || n > p->n_max) return MCF_E_ARG;
+    o->precision = p->precision;
+    const int bytes = p->precision == MCF_FP32 ? 4 : 8;
+    if (pool_org_for(n, bytes) == 1) {
+        const int vec = 16 / bytes;
+        o->kernel_mode = MCF_KERNELS_TWO_PHASE;
+        o->edge_waves = -1;
+        o->edge_vectors = n <= 64 * vec ? 1 : n <= 128 * vec ? 2 : 4;
+        o->node_block = 64;
+    } else {
+        o->kernel_mode = MCF_KERNELS_FUSED;
+        o->edge_waves = o->edge_vectors = o->node_block = 0;
+    }
+    return MCF_OK;
 }
 
 int mcf_pool_shape(const mcf_pool *p, int32_t *waves, int32_t *grid, int32_t *max_ept)

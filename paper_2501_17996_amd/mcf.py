@@ -34,7 +34,7 @@ EXPORTED = [
     "mcf_reset",
     "mcf_status", "mcf_get_solution", "mcf_get_state", "mcf_set_state", "mcf_destroy", "mcf_strerror",
     "mcf_solve_static", "mcf_debug_poison", "mcf_enable_kernel_timing", "mcf_kernel_time", "mcf_layout", "mcf_edge_shapes",
-    "mcf_pool_options_default", "mcf_pool_create", "mcf_pool_shape", "mcf_pool_admit", "mcf_pool_step", "mcf_pool_sync", "mcf_pool_poll", "mcf_pool_retire",
+    "mcf_pool_options_default", "mcf_pool_create", "mcf_pool_shape", "mcf_pool_instance_options", "mcf_pool_admit", "mcf_pool_step", "mcf_pool_sync", "mcf_pool_poll", "mcf_pool_retire",
     "mcf_pool_info", "mcf_pool_destroy",
 ]
 MCF_POOL_MAX_SLOTS = 256
@@ -121,6 +121,7 @@ def lib():
         L.mcf_pool_options_default.restype = None
         L.mcf_pool_create.argtypes = [ctypes.POINTER(mcf_pool_options), ctypes.POINTER(_vp)]
         L.mcf_pool_shape.argtypes = [_vp, _ip, _ip, _ip]
+        L.mcf_pool_instance_options.argtypes = [_vp, ctypes.c_int32, ctypes.POINTER(mcf_options)]
         L.mcf_pool_admit.argtypes = [_vp, _vp, _ip]
         L.mcf_pool_step.argtypes = [_vp, ctypes.c_int32]
         L.mcf_pool_sync.argtypes = [_vp]
@@ -368,6 +369,17 @@ def mcf_pool_shape(p) -> dict:
     return {"waves": w.value, "grid": g.value, "max_ept": e.value}
 
 
+POOL_INSTANCE_FIELDS = ("precision", "kernel_mode", "edge_waves", "edge_vectors", "node_block")
+
+
+def mcf_pool_instance_options(p, n: int) -> dict:
+    """The precision, organisation and launch shape an instance of n nodes should be created
+    with to run in this pool (keyword arguments of Solver)."""
+    o = mcf_options_default()
+    _check(lib().mcf_pool_instance_options(p, int(n), ctypes.byref(o)), "mcf_pool_instance_options")
+    return {k: int(getattr(o, k)) for k in POOL_INSTANCE_FIELDS}
+
+
 def mcf_pool_admit(p, s) -> int:
     slot = ctypes.c_int32()
     _check(lib().mcf_pool_admit(p, s, ctypes.byref(slot)), "mcf_pool_admit")
@@ -415,6 +427,9 @@ class Pool:
 
     def shape(self) -> dict:
         return mcf_pool_shape(self.h)
+
+    def instance_options(self, n: int) -> dict:
+        return mcf_pool_instance_options(self.h, n)
 
     def admit(self, solver: "Solver") -> int:
         return mcf_pool_admit(self.h, solver.h)

@@ -119,6 +119,8 @@ class GpuBackend:
         return inst.n <= self.mcf.FUSED_MAX_N
 
     def footprint(self, inst) -> int:
+        # the workspace of the organisation the pool will run (mcf_workspace_bytes gives AUTO's;
+        # the two-phase one needs no second copy of F, so this bound holds for both)
         return self.mcf.mcf_workspace_bytes(inst.n, inst.m, self.precision)
 
     def create(self, inst):
@@ -126,9 +128,11 @@ class GpuBackend:
         if got is None:
             return None
         off, ln = got
-        s = self.mcf.Solver(inst, precision=self.precision, tol=self.tol, max_iter=self.max_iter,
-                            check_every=self.check_every, stream=self.setup_stream.cuda_stream,
-                            workspace=self.base + off, workspace_bytes=ln, adapt_until=self.adapt_until)
+        # the organisation and launch shape the pool runs fastest for this size
+        shape = self.pool.instance_options(inst.n)
+        s = self.mcf.Solver(inst, tol=self.tol, max_iter=self.max_iter, check_every=self.check_every,
+                            stream=self.setup_stream.cuda_stream, workspace=self.base + off, workspace_bytes=ln,
+                            adapt_until=self.adapt_until, **shape)
         s.arena_block = got
         return s
 

@@ -17,9 +17,11 @@ With ``--pool`` it tunes the batching pool instead: for each bucket b of the lar
 admits (64, 128, 256, 512) it fills a pool with 64 instances of n uniform in (b/2, b],
 out-degree uniform in 4..16, half log and half power(1/2) utility (the shape of the serving
 stream), and times a pool iteration over all of them (events on the pool's stream, after
-warm-up steps) with each compiled number of waves per node workgroup; the fastest goes into
-``csrc/tuned_pool.inc``, which a pool looks up by its n_max.  The choice is a function of
-(n_max, precision) alone.
+warm-up steps) with each compiled number of waves per node workgroup, and with every instance
+in the two-phase iteration instead (flat edge items, then node items); the fastest goes into
+``csrc/tuned_pool.inc``: a pool takes the waves of the entry for its n_max, and an instance of n
+nodes the organisation of the entry for n (``mcf_pool_instance_options``).  The choice is a
+function of (n, precision) alone.
 
     python -m paper_2501_17996_amd.tune --pool [--summary FILE]
 """
@@ -85,7 +87,7 @@ def tune(sizes, log=print):
 
 POOL_INC = os.path.join(HERE, "csrc", "tuned_pool.inc")
 POOL_BUCKETS = (64, 128, 256, 512)
-POOL_WAVES = {1: (4, 8), 0: (8,)}     # compiled waves per node workgroup, per precision
+POOL_WAVES = {1: (1, 2, 4, 8), 0: (8,)}  # compiled waves per node workgroup, per precision
 
 
 def pool_instances(b: int, slots: int = 64):
@@ -100,11 +102,20 @@ def pool_instances(b: int, slots: int = 64):
     return out
 
 
-def time_pool(mcf, torch, insts, precision, b, waves, steps=8, K=20):
-    """Microseconds per pool iteration over every instance (tolerance out of reach)."""
+def two_phase_options(mcf, n, precision):
+    """The two-phase form a pool runs: flat edge phase, 64-thread node blocks."""
+    vec = 4 if precision == 1 else 2
+    nv = 1 if n <= 64 * vec else 2 if n <= 128 * vec else 4
+    return dict(kernel_mode=mcf.MCF_KERNELS_TWO_PHASE, edge_waves=-1, edge_vectors=nv, node_block=64)
+
+
+def time_pool(mcf, torch, insts, precision, b, waves, org=0, steps=8, K=20):
+    """Microseconds per pool iteration over every instance (tolerance out of reach); org 1 creates
+    every instance in the two-phase iteration."""
     stream = torch.cuda.Stream()
     pool = mcf.Pool(precision, 0, len(insts), K, stream=stream.cuda_stream, n_max=b, waves=waves)
-    hs = [mcf.Solver(i, precision=precision, tol=1e-14, check_every=K, max_iter=10 ** 8) for i in insts]
+    hs = [mcf.Solver(i, precision=precision, tol=1e-14, check_every=K, max_iter=10 ** 8,
+                     **(two_phase_options(mcf, i.n, precision) if org else {})) for i in insts]
     try:
         for h in hs:
             pool.admit(h)
@@ -136,9 +147,12 @@ def tune_pool(log=print):
             rows = []
             for waves in POOL_WAVES[precision]:
                 us = time_pool(mcf, torch, insts, precision, b, waves)
-                rows.append((us, waves))
-                log(f"pool {'fp32' if precision else 'fp64'} n_max={b:3d} waves={waves}: {us:8.2f} us/iteration "
+                rows.append((us, waves, 0))
+                log(f"pool {'fp32' if precision else 'fp64'} n_max={b:3d} fused waves={waves}: {us:8.2f} us/iteration "
                     f"({sum(i.n for i in insts)} nodes)")
+            us = time_pool(mcf, torch, insts, precision, b, POOL_WAVES[precision][-1], org=1)
+            rows.append((us, 0, 1))
+            log(f"pool {'fp32' if precision else 'fp64'} n_max={b:3d} two-phase: {us:8.2f} us/iteration")
             rows.sort()
             results[(precision, b)] = rows
     return results
@@ -148,14 +162,16 @@ def write_pool_inc(results, path=POOL_INC):
     lines = ["// Batching-pool launch shapes by measurement, written by paper_2501_17996_amd/tune.py (--pool)",
              "// on one MI355X: 64 instances of n in (n_max/2, n_max], out-degree 4..16, log and power(1/2);",
              "// mean time of a pool iteration over all of them.  Entries ascend in n_max per iterate size:",
-             "// {bytes, largest n of the pool, waves per node workgroup}.",
+             "// {bytes, largest n, waves per node workgroup of the fused items, organisation of an instance of",
+             "// that size: 0 fused, 1 two-phase}.",
              "static const TunedPool TUNED_POOL[] = {"]
     for precision in (1, 0):
         for b in POOL_BUCKETS:
             rows = results.get((precision, b))
             if rows:
-                us, waves = rows[0]
-                lines.append(f"    {{{4 if precision else 8}, {b}, {waves}}},  // {us:.2f} us")
+                fused = [r for r in rows if r[2] == 0]
+                us, waves, org = rows[0]
+                lines.append(f"    {{{4 if precision else 8}, {b}, {fused[0][1]}, {org}}},  // {us:.2f} us")
     lines.append("};")
     with open(path, "w") as f:
         f.write("\n".join(lines) + "\n")
@@ -169,13 +185,14 @@ def write_pool_summary(results, path):
                 "check every 20 iterations included), events on the pool's stream after 3 warm-up steps. The "
                 "first row of each bucket is the one the table takes.\n\n")
         f.write("```\npython -m paper_2501_17996_amd.tune --pool --summary profiles/tuning_pool_shapes.md\n```\n\n")
-        f.write("| precision | n_max | waves per node | us per pool iteration | vs best |\n|---|---|---|---|---|\n")
+        f.write("| precision | n_max | organisation | waves per node | us per pool iteration | vs best |\n"
+                "|---|---|---|---|---|---|\n")
         for precision in (1, 0):
             for b in POOL_BUCKETS:
                 rows = results.get((precision, b), [])
-                for us, waves in rows:
-                    f.write(f"| {'FP32' if precision else 'FP64'} | {b} | {waves} | {us:.2f} | "
-                            f"{us / rows[0][0]:.3f} |\n")
+                for us, waves, org in rows:
+                    f.write(f"| {'FP32' if precision else 'FP64'} | {b} | {'two-phase' if org else 'fused'} | "
+                            f"{waves if not org else '-'} | {us:.2f} | {us / rows[0][0]:.3f} |\n")
 
 
 ENTRY = re.compile(r"^\s*\{(\d+), (\d+), \{(\d+), (\d+), (\d+)\}, (\d+)\},\s*//\s*([0-9.]+) us")

@@ -276,7 +276,7 @@ def test_pool_fp64_matches_oracle_at_checkpoints(M):
     pool.close()
 
 
-@pytest.mark.parametrize("step,waves", [(K, 8), (7, 8), (K, 4)])
+@pytest.mark.parametrize("step,waves", [(K, 8), (7, 8), (K, 4), (7, 2), (7, 1)])
 def test_pool_graphs_equal_direct_launches(M, step, waves):
     """Steps replayed from captured graphs (keyed by the step length and the iterations where
     some instance adapts omega) give bitwise the results of launching every kernel directly.
@@ -311,12 +311,13 @@ def test_pool_graphs_equal_direct_launches(M, step, waves):
         np.testing.assert_array_equal(a[3], b[3])
 
 
-def test_pool_four_waves_alone_equals_mix(M):
-    """The 4-wave node workgroup (FP32): alone and in the mix bitwise, and the same iterate
-    as the 8-wave shape up to the order of its sums."""
+@pytest.mark.parametrize("small", [4, 2, 1])
+def test_pool_fewer_waves_alone_equals_mix(M, small):
+    """The 4-, 2- and 1-wave node workgroups (FP32): alone and in the mix bitwise, and the same
+    solution as the 8-wave shape up to the order of its sums."""
     insts = _mix()
     res = {}
-    for waves in (4, 8):
+    for waves in (small, 8):
         pool = M.Pool(1, max_slots=len(insts), check_every=K, waves=waves)
         hs = [_solver(M, inst, 1, 1e-4) for inst in insts]
         sls = [pool.admit(h) for h in hs]
@@ -324,15 +325,15 @@ def test_pool_four_waves_alone_equals_mix(M):
         res[waves] = [mix[sl] for sl in sls]
         pool.close()
     for q in (0, 5):
-        pool = M.Pool(1, max_slots=1, check_every=K, waves=4)
+        pool = M.Pool(1, max_slots=1, check_every=K, waves=small)
         h = _solver(M, insts[q], 1, 1e-4)
         sl = pool.admit(h)
         alone = _drain(M, pool, [h], [sl])[sl]
         pool.close()
-        assert alone[0]["iters"] == res[4][q][0]["iters"]
-        np.testing.assert_array_equal(alone[1], res[4][q][1])
-        np.testing.assert_array_equal(alone[2], res[4][q][2])
-    for a, b in zip(res[4], res[8]):
+        assert alone[0]["iters"] == res[small][q][0]["iters"]
+        np.testing.assert_array_equal(alone[1], res[small][q][1])
+        np.testing.assert_array_equal(alone[2], res[small][q][2])
+    for a, b in zip(res[small], res[8]):
         assert a[0]["state_name"] == b[0]["state_name"] == "converged"
         rel = abs(a[0]["primal_obj"] - b[0]["primal_obj"]) / max(1.0, abs(b[0]["primal_obj"]))
         assert rel <= 1e-5
@@ -431,3 +432,98 @@ def test_slow_instance_in_the_pool_tracks_the_oracle(M):
     assert st["rel_kkt"] > 1e-2 and mo["rel_kkt"] > 1e-2
     print(f"slow instance at k=1000: rel_kkt {st['rel_kkt']:.3e} (oracle {mo['rel_kkt']:.3e}), "
           f"omega {sg['omega']:.4g}", flush=True)
+
+
+def _two_phase_kw(M, n, precision):
+    """The two-phase form the pool runs: flat edge phase with the fewest vectors per lane that hold
+    n, 64-thread node blocks."""
+    vec = 4 if precision == 1 else 2
+    nv = 1 if n <= 64 * vec else 2 if n <= 128 * vec else 4
+    return dict(kernel_mode=M.MCF_KERNELS_TWO_PHASE, edge_waves=-1, edge_vectors=nv, node_block=64)
+
+
+def _mixed_solvers(M, insts, precision, tol, max_iter=60000):
+    """Even-indexed instances in the two-phase iteration, odd ones fused."""
+    return [M.Solver(inst, precision=precision, tol=tol, check_every=K, max_iter=max_iter,
+                     **(_two_phase_kw(M, inst.n, precision) if q % 2 == 0 else {}))
+            for q, inst in enumerate(insts)]
+
+
+def test_pool_two_phase_slots_match_oracle(M):
+    """Two-phase instances in the pool (flat edge items, then node items, each launch covering
+    every two-phase slot) beside fused ones, FP64: at pool checkpoints k = 20, 100 and 200 each
+    instance's F, Y and omega match the oracle's to 1e-10 and its check metrics match too."""
+    insts = _mix()
+    pool = M.Pool(0, max_slots=len(insts), check_every=K)
+    hs = _mixed_solvers(M, insts, 0, 1e-13)
+    assert [h.layout()["kernel_mode"] for h in hs[:2]] == ["two_phase", "fused"]
+    live = {pool.admit(h): q for q, h in enumerate(hs)}
+    orcs = [oracle.OracleSolver(inst, threads=THREADS) for inst in insts]
+    done = 0
+    for k in (20, 100, 200):
+        while done < k:
+            pool.step(K)
+            pool.sync()
+            done += K
+        recs = {q: pool.poll(sl) for sl, q in live.items()}
+        for sl in list(live):
+            pool.retire(sl)
+        for q, inst in enumerate(insts):
+            O = orcs[q]
+            O.run(k - int(O.get_state()[2]["k"]) - 1, check=False)
+            mo = O.step(check=True)
+            Fg, Yg, sg = hs[q].get_state()
+            Fo, Yo, so = O.get_state()
+            assert sg["k"] == so["k"] == k
+            ef, ey = _relerr(Fg, Fo), _relerr(Yg, Yo)
+            assert ef <= 1e-10 and ey <= 1e-10, (q, k, ef, ey)
+            assert sg["omega"] == pytest.approx(so["omega"], rel=1e-10)
+            g = recs[q]
+            for key in ("primal_obj", "dual_obj"):
+                if math.isfinite(mo[key]):
+                    assert g[key] == pytest.approx(mo[key], rel=1e-10, abs=1e-12), (q, k, key)
+                else:
+                    assert g[key] == mo[key]
+            assert_infeasible_count_exact(g, mo, hs[q], O, what=f"pool instance {q} k {k}")
+        live = {pool.admit(h): q for q, h in enumerate(hs)}
+    pool.close()
+
+
+@pytest.mark.parametrize("graphs", [1, 0])
+def test_pool_mixed_organisations_alone_equals_mix(M, graphs):
+    """FP32: each instance gives bitwise the same result alone in a one-slot pool and in the mix of
+    both organisations, with steps replayed from graphs or launched directly."""
+    insts = _mix()
+    pool = M.Pool(1, max_slots=len(insts), check_every=K, graphs=graphs)
+    hs = _mixed_solvers(M, insts, 1, 1e-4)
+    sls = [pool.admit(h) for h in hs]
+    mix = _drain(M, pool, hs, sls)
+    pool.close()
+    for q in (0, 2, 5):
+        pool = M.Pool(1, max_slots=1, check_every=K, graphs=1)
+        h = _mixed_solvers(M, [insts[q]] * (q % 2 + 1), 1, 1e-4)[q % 2]
+        sl = pool.admit(h)
+        alone = _drain(M, pool, [h], [sl])[sl]
+        pool.close()
+        b = mix[sls[q]]
+        assert alone[0]["state_name"] == b[0]["state_name"] == "converged"
+        assert alone[0]["iters"] == b[0]["iters"]
+        for x, y in zip(alone[1:], b[1:]):
+            np.testing.assert_array_equal(x, y)
+
+
+def test_pool_two_phase_admission(M):
+    """A two-phase instance is admitted only in the form the pool runs; instance_options gives it."""
+    pool = M.Pool(1, max_slots=2, check_every=K)
+    inst = _mix()[2]                                        # n = 150
+    other = M.Solver(inst, precision=1, tol=1e-4, kernel_mode=M.MCF_KERNELS_TWO_PHASE, edge_waves=1,
+                     edge_vectors=1, node_block=64)         # the concurrent edge phase
+    with pytest.raises(M.MCFError) as ei:
+        pool.admit(other)
+    assert ei.value.code == M.MCF_E_ARG
+    kw = pool.instance_options(inst.n)
+    assert kw["precision"] == 1 and kw["kernel_mode"] in (M.MCF_KERNELS_FUSED, M.MCF_KERNELS_TWO_PHASE)
+    pool.admit(M.Solver(inst, tol=1e-4, **kw))
+    pool.admit(M.Solver(inst, precision=1, tol=1e-4, **_two_phase_kw(M, inst.n, 1)))
+    with pytest.raises(M.MCFError):
+        pool.instance_options(600)
