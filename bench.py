@@ -551,6 +551,11 @@ def main():
             if "extras" in out:
                 cb = cpu_baseline_solve(workload("c2")[0], 1e-4, 50, args.cpu_budget)
                 p_c2 = cb.pop("primal_obj")
+                # one host thread, per iteration (a config4 iteration takes over a minute on one thread)
+                c2 = workload("c2")[0]
+                med1, _ = cpu_baseline_iterations(c2, 5, 1)
+                cb["one_thread"] = {"value": c2.n * c2.m / med1, "s_per_iteration": med1,
+                                    "sample": "median of 5 FP64 iterations from the cold start on 1 thread"}
                 out["extras"]["c2"]["cpu_baseline"] = cb
         else:
             cb = cpu_baseline_solve(inst, tol, args.check_every, args.cpu_budget)

@@ -163,7 +163,8 @@ def test_graph_not_strongly_connected(mcf):
 def test_pool_argument_validation(mcf):
     """Invalid pool options are refused on the host, before any device call."""
     bad = [dict(precision=7), dict(max_slots=0), dict(max_slots=mcf.MCF_POOL_MAX_SLOTS + 1), dict(check_every=0),
-           dict(n_max=1), dict(n_max=513), dict(waves=6), dict(waves=16), dict(precision=0, waves=4),
+           dict(n_max=1), dict(n_max=513), dict(waves=6), dict(waves=16), dict(waves=3), dict(precision=0, waves=4),
+           dict(precision=0, waves=2),
 ]
     for kw in bad:
         args = {"precision": 1, "hbm_budget": 0, "max_slots": 4, "check_every": 20}

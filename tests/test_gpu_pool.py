@@ -354,9 +354,9 @@ def test_pool_n_max_limits_admission_and_shape(M):
 
 def test_serve_loop_on_the_gpu_equals_alone(M):
     """serve() through the GPU backend: twelve requests of the serving stream on three slots,
-    admitted as slots free up.  Each request's result equals that instance run alone in a
-    one-slot pool of the same shape (iterations and objective exactly), and every arena block
-    is returned."""
+    admitted as slots free up, each in the organisation the pool gives its size.  Each request's
+    result equals that instance run alone in a one-slot pool of the same shape (iterations and
+    objective exactly), and every arena block is returned."""
     from paper_2501_17996_amd.serve import GpuBackend, Request, serve
     reqs = [I.serving_request(r) for r in range(12)]
     budget = 3 * max(M.mcf_workspace_bytes(i.n, i.m, 1) for i in reqs) + (1 << 20)
@@ -369,7 +369,8 @@ def test_serve_loop_on_the_gpu_equals_alone(M):
     for rec in records:
         inst = I.serving_request(rec.rid)
         pool = M.Pool(1, max_slots=1, check_every=K)
-        h = M.Solver(inst, precision=1, tol=1e-4, check_every=K, max_iter=60000, adapt_until=1000)
+        h = M.Solver(inst, tol=1e-4, check_every=K, max_iter=60000, adapt_until=1000,
+                     **pool.instance_options(inst.n))    # the organisation serve() gives it
         sl = pool.admit(h)
         st = _drain(M, pool, [h], [sl], limit=4000)[sl][0]
         pool.close()
