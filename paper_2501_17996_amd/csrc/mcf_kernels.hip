@@ -475,14 +475,17 @@ __global__ __launch_bounds__(WPE == 1 ? 256 : 64 * WPE) void edge_kernel(Consts 
         const double cap = b.cap[e];
         const double mu0 = b.mu[e];
         // All 3 NV loads are issued before any is used: a vector past n reads the column's
-        // first vector instead (always in bounds) and is then replaced by zeros.
+        // first vector instead (always in bounds) and is then replaced by zeros.  F streams
+        // (non-temporal loads and stores: each column is touched once per phase); Y[:,head]
+        // takes ordinary loads, since each column of Y is read again at every edge that ends
+        // there and the caches can serve some of those reads.
         T fo[NV][VEC], q[NV][VEC], bh[NV][VEC], bt[NV][VEC];
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             const int i = (v * LANES + t) * VEC;
             const int ic = i < n ? i : 0;
             vload_nt(f + ic, fo[v]);
-            vload_nt(yh + ic, bh[v]);
+            vload(yh + ic, bh[v]);
             vload(yt + ic, bt[v]);
         }
 #pragma unroll
@@ -650,7 +653,7 @@ __device__ __forceinline__ void wave_edge(const Consts &c, const Bufs<T> &b, int
         const int i = (v * 64 + t) * VEC;
         const int ic = i < n ? i : 0;
         vload_nt(f + ic, fo[v]);
-        vload_nt(yh + ic, bh[v]);
+        vload(yh + ic, bh[v]);
         vload(yt + ic, bt[v]);
     }
 #pragma unroll
@@ -977,12 +980,14 @@ __device__ __forceinline__ void node_body(const Consts &c, const Bufs<T> &b, con
             w = (double)wt;
             b.P[x] = (T)pn;
         } else {
+            // Sout, P and W are touched once per iteration: non-temporal, like F in the edge
+            // phase, so that the caches keep Y, which the edge phase reads again per edge end
             pn = flat ? p_entry_flat<T>(b.F, b.in_edge, i0, i1, b.out_off[j], b.out_off[j + 1], ld, i)
-                      : p_entry<T>(b.F, b.in_edge, i0, i1, b.Sout[x], ld, i);
-            po = (double)b.P[x];
-            b.P[x] = (T)pn;
+                      : p_entry<T>(b.F, b.in_edge, i0, i1, __builtin_nontemporal_load(b.Sout + x), ld, i);
+            po = (double)__builtin_nontemporal_load(b.P + x);
+            __builtin_nontemporal_store((T)pn, b.P + x);
             y = (double)b.Y[x];
-            w = (double)b.W[x];
+            w = (double)__builtin_nontemporal_load(b.W + x);
         }
         const double v = fma(2.0 / c.rho, pn, -(((2.0 - c.rho) / c.rho) * po));
         const double yhat = (i != j) ? prox_dual<UTIL>(y - beta * v, beta, w, g, c.c1, -y) : 0.0;

@@ -110,12 +110,14 @@ def two_phase_options(mcf, n, precision):
 
 
 def time_pool(mcf, torch, insts, precision, b, waves, org=0, steps=8, K=20):
-    """Microseconds per pool iteration over every instance (tolerance out of reach); org 1 creates
-    every instance in the two-phase iteration."""
+    """Microseconds per pool iteration over every instance (tolerance out of reach).  org: 0 every
+    instance fused, 1 every instance in the two-phase iteration, or a predicate on n choosing
+    the two-phase iteration for some."""
     stream = torch.cuda.Stream()
     pool = mcf.Pool(precision, 0, len(insts), K, stream=stream.cuda_stream, n_max=b, waves=waves)
+    two = org if callable(org) else (lambda n: bool(org))
     hs = [mcf.Solver(i, precision=precision, tol=1e-14, check_every=K, max_iter=10 ** 8,
-                     **(two_phase_options(mcf, i.n, precision) if org else {})) for i in insts]
+                     **(two_phase_options(mcf, i.n, precision) if two(i.n) else {})) for i in insts]
     try:
         for h in hs:
             pool.admit(h)
@@ -138,9 +140,12 @@ def time_pool(mcf, torch, insts, precision, b, waves, org=0, steps=8, K=20):
 
 def tune_pool(log=print):
     import torch
+    from . import instances as I
     from . import mcf
     torch.cuda.set_device(0)
-    results = {}   # (precision, b) -> sorted [(us, waves)]
+    results = {}   # (precision, b) -> sorted [(us, waves, org)]
+    orgs = {}      # (precision, b) -> organisation of that bucket's instances in a mixed pool
+    mix = [I.serving_request(r) for r in range(64)]
     for precision in (1, 0):
         for b in POOL_BUCKETS:
             insts = pool_instances(b)
@@ -155,6 +160,23 @@ def tune_pool(log=print):
             log(f"pool {'fp32' if precision else 'fp64'} n_max={b:3d} two-phase: {us:8.2f} us/iteration")
             rows.sort()
             results[(precision, b)] = rows
+        # The organisation of an instance is decided in a mixed pool (the first 64 requests of the
+        # serving stream, with the waves measured best for n_max = 512): a bucket's instances go
+        # two-phase only if the pool is faster with them so than with every instance fused, since
+        # the two-phase launches cost their latency whatever the number of instances in them.
+        waves = sorted(r for r in results[(precision, 512)] if r[2] == 0)[0][1]
+        base = time_pool(mcf, torch, mix, precision, 512, waves, org=0)
+        log(f"pool {'fp32' if precision else 'fp64'} serving mix, all fused: {base:8.2f} us/iteration")
+        orgs[(precision, 0)] = base
+        lo = 0
+        for b in POOL_BUCKETS:
+            us = time_pool(mcf, torch, mix, precision, 512, waves, org=lambda n, lo=lo, b=b: lo < n <= b)
+            orgs[(precision, b)] = 1 if us < 0.99 * base else 0
+            log(f"pool {'fp32' if precision else 'fp64'} serving mix, n in ({lo}, {b}] two-phase: {us:8.2f} "
+                f"us/iteration -> {'two-phase' if orgs[(precision, b)] else 'fused'}")
+            results[(precision, b)].append((us, -b, 2))   # a mixed-pool row (listed, not a shape)
+            lo = b
+    results["orgs"] = orgs
     return results
 
 
@@ -163,15 +185,16 @@ def write_pool_inc(results, path=POOL_INC):
              "// on one MI355X: 64 instances of n in (n_max/2, n_max], out-degree 4..16, log and power(1/2);",
              "// mean time of a pool iteration over all of them.  Entries ascend in n_max per iterate size:",
              "// {bytes, largest n, waves per node workgroup of the fused items, organisation of an instance of",
-             "// that size: 0 fused, 1 two-phase}.",
+             "// that size: 0 fused, 1 two-phase}.  The organisation is decided in a mixed pool (64 requests of",
+             "// the serving stream): two-phase only where moving that size's instances there made it faster.",
              "static const TunedPool TUNED_POOL[] = {"]
     for precision in (1, 0):
         for b in POOL_BUCKETS:
             rows = results.get((precision, b))
             if rows:
-                fused = [r for r in rows if r[2] == 0]
-                us, waves, org = rows[0]
-                lines.append(f"    {{{4 if precision else 8}, {b}, {fused[0][1]}, {org}}},  // {us:.2f} us")
+                fused = sorted(r for r in rows if r[2] == 0)
+                org = results["orgs"][(precision, b)]
+                lines.append(f"    {{{4 if precision else 8}, {b}, {fused[0][1]}, {org}}},  // {fused[0][0]:.2f} us")
     lines.append("};")
     with open(path, "w") as f:
         f.write("\n".join(lines) + "\n")
@@ -189,10 +212,25 @@ def write_pool_summary(results, path):
                 "|---|---|---|---|---|---|\n")
         for precision in (1, 0):
             for b in POOL_BUCKETS:
-                rows = results.get((precision, b), [])
+                rows = [r for r in results.get((precision, b), []) if r[2] < 2]
                 for us, waves, org in rows:
                     f.write(f"| {'FP32' if precision else 'FP64'} | {b} | {'two-phase' if org else 'fused'} | "
                             f"{waves if not org else '-'} | {us:.2f} | {us / rows[0][0]:.3f} |\n")
+        f.write("\nThe organisation of an instance is decided in a mixed pool: the first 64 requests of the serving "
+                "stream, with the bucket's instances in the two-phase iteration and the others fused, against all "
+                "fused (the two-phase launches cost their latency whatever the number of instances in them).\n\n")
+        f.write("| precision | two-phase instances | us per pool iteration | table |\n|---|---|---|---|\n")
+        for precision in (1, 0):
+            if (precision, 0) in results["orgs"]:
+                f.write(f"| {'FP32' if precision else 'FP64'} | none | {results['orgs'][(precision, 0)]:.2f} | |\n")
+            lo = 0
+            for b in POOL_BUCKETS:
+                mixed = [r for r in results.get((precision, b), []) if r[2] == 2]
+                if mixed:
+                    org = results["orgs"][(precision, b)]
+                    f.write(f"| {'FP32' if precision else 'FP64'} | n in ({lo}, {b}] | {mixed[0][0]:.2f} | "
+                            f"{'two-phase' if org else 'fused'} |\n")
+                lo = b
 
 
 ENTRY = re.compile(r"^\s*\{(\d+), (\d+), \{(\d+), (\d+), (\d+)\}, (\d+)\},\s*//\s*([0-9.]+) us")
