@@ -1213,6 +1213,9 @@ int pool_upload(mcf_pool *p)
         if (!p->desc[sl].c.fused) ne_need += p->desc[sl].c.nep;
     if (ne_need > p->ework_cap) {  // grow the edge-item lists (the stream is idle)
         const size_t cap = std::max(ne_need, 2 * p->ework_cap);
+        // every graph captured so far holds the old list's address in its kernel arguments
+        for (auto &g : p->graphs_cache) (void)hipGraphExecDestroy(g.second.first);
+        p->graphs_cache.clear();
         if (p->d_ework) (void)hipFree(p->d_ework);
         if (p->h_ework) (void)hipHostFree(p->h_ework);
         p->d_ework = nullptr;

@@ -528,3 +528,32 @@ def test_pool_two_phase_admission(M):
     pool.admit(M.Solver(inst, precision=1, tol=1e-4, **_two_phase_kw(M, inst.n, 1)))
     with pytest.raises(M.MCFError):
         pool.instance_options(600)
+
+
+def test_pool_edge_list_growth_keeps_graphs_valid(M):
+    """Two-phase slots admitted one at a time, with a step between admissions, so that the pool's
+    list of flat edge items grows while graphs of earlier steps are cached (the first growth keeps
+    the same launch grid, so the same step key comes back): the graphs captured before a growth
+    are dropped with the old list, and every instance's result equals that of the same sequence
+    launched without graphs."""
+    insts = [_mix()[q] for q in (0, 2, 4)]                  # n = 12, 150, 400: 5, 150, 300 edge items
+
+    def run(graphs):
+        pool = M.Pool(1, max_slots=3, check_every=K, graphs=graphs)
+        hs = [M.Solver(inst, precision=1, tol=1e-4, check_every=K, max_iter=60000, **_two_phase_kw(M, inst.n, 1))
+              for inst in insts]
+        sls = []
+        for h in hs:
+            sls.append(pool.admit(h))
+            pool.step(K)
+            pool.sync()
+        out = _drain(M, pool, hs, sls)
+        pool.close()
+        return [out[sl] for sl in sls]
+
+    with_graphs, direct = run(1), run(0)
+    for q, (x, y) in enumerate(zip(with_graphs, direct)):
+        assert x[0]["state_name"] == y[0]["state_name"] == "converged", q
+        assert x[0]["iters"] == y[0]["iters"], q
+        for u, v in zip(x[1:], y[1:]):
+            np.testing.assert_array_equal(u, v)
