@@ -584,6 +584,64 @@ def test_c4_late_iteration_sampled_with_check(M):
     _sampled_step_check(M, inst, 1, iters_before=2000, n_edges=200, n_nodes=20, seed=4, check=True)
 
 
+def test_c4_late_check_metrics_against_oracle(M):
+    """config4, FP32 iterates, whole instance (not sampled): from the GPU state after 1999
+    iterations, one checked iteration on the GPU and one in the oracle (FP64, from the same state),
+    and every check quantity the stop decision reads is compared: the objectives p and d, the
+    residual r of (e-res), rel_primal, rel_dual, rel_gap, rel_kkt and the count of pairs with
+    T^ <= 0.  Tolerances are those of FP32 iterates: q, Fhat and D carry a relative rounding of
+    about 2^-24 per entry (6e-8), sums of many such entries about as much, and r = a - b^2/e
+    cancels, so rel_dual^2 = r/a gets an absolute floor of 1e-5 as a share of a."""
+    import ctypes
+    inst = I.config4(0)
+    n = inst.n
+    S = gpu_solver(M, inst, precision=1, check_every=1999)
+    S.run(1999)
+    F0, Y0, sc0 = S.get_state()
+    O = oracle.OracleSolver(inst, threads=THREADS)
+    O.set_state(F0, Y0, sc0["k"], sc0["omega"])
+    del F0, Y0
+    g = S.run(1)
+    o = O.step(check=True)
+    assert g["iters"] == int(o["k"]) == 2000
+    print(f"config4 k=2000: p {g['primal_obj']:.9e} / {o['primal_obj']:.9e}, d {g['dual_obj']:.9e} / "
+          f"{o['dual_obj']:.9e}, rel_primal {g['rel_primal']:.4e} / {o['rel_primal']:.4e}, rel_dual "
+          f"{g['rel_dual']:.4e} / {o['rel_dual']:.4e}, rel_gap {g['rel_gap']:.4e} / {o['rel_gap']:.4e}, "
+          f"infeasible {g['infeasible_frac']:.3e} / {o['infeasible_frac']:.3e}", flush=True)
+    for key in ("primal_obj", "dual_obj"):
+        a, b = g[key], o[key]
+        if math.isfinite(b):
+            assert a == pytest.approx(b, rel=1e-5), key
+        else:
+            assert a == b, key
+    if math.isfinite(o["rel_primal"]):
+        assert abs(g["rel_primal"] - o["rel_primal"]) <= 1e-4 * o["rel_primal"] + 1e-6
+    if math.isfinite(o["rel_gap"]):
+        assert abs(g["rel_gap"] - o["rel_gap"]) <= 1e-4 * abs(o["rel_gap"]) + 1e-6
+    if math.isfinite(o["rel_dual"]):
+        assert abs(g["rel_dual"] ** 2 - o["rel_dual"] ** 2) <= 1e-4 * o["rel_dual"] ** 2 + 1e-5
+        assert abs(g["r"] - o["r"]) <= 1e-4 * abs(o["r"]) + 1e-5 * o["a"]
+    if math.isfinite(o["rel_kkt"]):
+        assert abs(g["rel_kkt"] - o["rel_kkt"]) <= 1e-4 * o["rel_kkt"] + 1e-5
+    else:
+        assert g["rel_kkt"] == o["rel_kkt"]
+    # the count of pairs with T^ <= 0: equal, except at pairs whose oracle T^ lies within FP32
+    # rounding of 0 (1e-5 of the largest entry), where either sign is a correct rounding
+    pairs = n * (n - 1)
+    cg, co = round(g["infeasible_frac"] * pairs), round(o["infeasible_frac"] * pairs)
+    if cg != co:
+        Tg, To = np.empty(n * n), np.empty(n * n)
+        assert M.lib().mcf_get_solution(S.h, None, Tg.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), None) == 0
+        oracle.lib().orc_get_last(O._h, None, To.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), None)
+        off = ~np.eye(n, dtype=bool).reshape(-1)
+        Tg, To = Tg[off], To[off]
+        tiny = np.abs(To) <= 1e-5 * float(np.max(np.abs(To)))
+        flipped = int(np.sum(((Tg <= 0) != (To <= 0)) & ~tiny))
+        assert flipped == 0 and abs(cg - co) <= int(np.sum(tiny)), f"infeasible count {cg} vs {co}"
+    O.close()
+    S.close()
+
+
 def test_c3_fp32_sampled(M):
     inst = I.config3(0)
     _sampled_step_check(M, inst, 1, iters_before=20, n_edges=20, n_nodes=6)
