@@ -1118,16 +1118,21 @@ __device__ __forceinline__ void fused_body(const Consts &c, const Bufs<T> &b, co
     const double beta = b.sc->beta, g = c.gamma, rho = c.rho, omr = 1.0 - c.rho;
     const int k0 = b.inc_off[j], k1 = b.inc_off[j + 1], deg = k1 - k0;
     const T *yj = Yc + (long long)j * ld;
-    // node-phase operands, loaded before the edge loop so their latency overlaps it (rows
-    // past n read row 0 and are never used)
+    // node-phase operands (rows past n read row 0 and are never used): loaded before the edge
+    // loop so that their latency overlaps it, unless they would hold more than 4 registers per
+    // thread across it (small workgroups with many rows per thread), which would cost occupancy
+    constexpr bool EARLY = RPT <= 2;
     T yrow[RPT], wrow[RPT];
+    auto load_rows = [&]() {
 #pragma unroll
-    for (int r = 0; r < RPT; ++r) {
-        const int i = threadIdx.x + r * 64 * NWV;
-        const int ic = i < n ? i : 0;
-        yrow[r] = yj[ic];
-        wrow[r] = b.W[(long long)j * ld + ic];
-    }
+        for (int r = 0; r < RPT; ++r) {
+            const int i = threadIdx.x + r * 64 * NWV;
+            const int ic = i < n ? i : 0;
+            yrow[r] = yj[ic];
+            wrow[r] = b.W[(long long)j * ld + ic];
+        }
+    };
+    if constexpr (EARLY) load_rows();
     // column j of Y, shared by every edge incident to j (its head or its tail column)
     T yjl[EPT];
 #pragma unroll
@@ -1278,6 +1283,7 @@ __device__ __forceinline__ void fused_body(const Consts &c, const Bufs<T> &b, co
     };
     chunk(0);
     for (int base = FUSED_INC_CHUNK; base < deg; base += FUSED_INC_CHUNK) chunk(base);
+    if constexpr (!EARLY) load_rows();
 #pragma unroll
     for (int jj = 0; jj < EPT; ++jj) {
         vsh[(wv * EPT + jj) * 64 + lane] = vacc[jj];
