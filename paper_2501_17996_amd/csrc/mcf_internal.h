@@ -39,6 +39,8 @@ struct Consts {
     int node_latency;      // 1: regular node launches in the latency form (F within NODE_LATENCY_BYTES)
     int nrp;               // partials of the residual pass (a, b; one per RES_EDGES edges)
     int edge_ept;          // 16-byte vectors per lane of the two-phase edge shape
+    int f_cached;          // 1: F within F_CACHED_BYTES, read and written with ordinary accesses by the
+                           // one-wave edge phases (else non-temporal)
 };
 
 // Algorithm 2.1 step 3 adapts omega at iterations k that are multiples of k_adapt (k = 0
@@ -63,6 +65,11 @@ constexpr int IN_EDGE_PAD = 16;
 // fewer loads in flight per wave is measurably faster (crossover between n = 3000 and 4096 at
 // out-degree 10 in FP32).
 constexpr long long NODE_LATENCY_BYTES = 512ll << 20;
+// Largest F (bytes) that the one-wave edge phases (concurrent and flat, n <= 2048) read and write
+// with ordinary loads and stores: an F that fits the Infinity Cache is then still there when the
+// node phase gathers it (config3, F = 40 MB: edge launch 20.1 -> 19.5 us, node 19.4 -> 18.8 us).
+// Larger ones stream with non-temporal accesses, which leave the caches to Y.
+constexpr long long F_CACHED_BYTES = 256ll << 20;
 
 // Offsets (in doubles) of the partial-sum segments.
 struct PartLayout {

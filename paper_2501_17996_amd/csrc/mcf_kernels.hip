@@ -625,7 +625,11 @@ __global__ __launch_bounds__(WPE == 1 ? 256 : 64 * WPE) void edge_kernel(Consts 
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
         const int i = (v * LANES + t) * VEC;
-        if (i < n) *reinterpret_cast<typename Vec<T>::type *>(sout + i) = so[v * NT];
+        if (i < n) {  // non-temporal: the node phase reads Sout once, and Y keeps the caches
+            T sv[VEC];
+            vload(reinterpret_cast<const T *>(so + v * NT), sv);
+            vstore_nt(sout + i, sv);
+        }
     }
 }
 
@@ -652,7 +656,8 @@ __device__ __forceinline__ void wave_edge(const Consts &c, const Bufs<T> &b, int
     for (int v = 0; v < NV; ++v) {
         const int i = (v * 64 + t) * VEC;
         const int ic = i < n ? i : 0;
-        vload_nt(f + ic, fo[v]);
+        if (c.f_cached) vload(f + ic, fo[v]);  // see F_CACHED_BYTES
+        else vload_nt(f + ic, fo[v]);
         vload(yh + ic, bh[v]);
         vload(yt + ic, bt[v]);
     }
@@ -738,7 +743,8 @@ __device__ __forceinline__ void wave_edge(const Consts &c, const Bufs<T> &b, int
                 }
             }
             if (OUTSUM) vstore(so + v * 64 * VEC, acc);
-            vstore_nt(f + i, fn);
+            if (c.f_cached) vstore(f + i, fn);
+            else vstore_nt(f + i, fn);
             if (CHECK) {
                 vstore_nt(b.Fhat + (long long)e * ld + i, fhv);
                 vstore_nt(b.D + (long long)e * ld + i, dv);

@@ -777,6 +777,7 @@ int prepare_solver(int32_t n, int32_t m, const int32_t *tail, const int32_t *hea
     c.nrp = (m + RES_EDGES - 1) / RES_EDGES;
     c.edge_ept = s->sh.ept;
     c.nnp = fused ? n : c.nblk_node;
+    c.f_cached = (long long)n * m * (o.precision == MCF_FP32 ? 4 : 8) <= F_CACHED_BYTES ? 1 : 0;
     *out = s;
     return MCF_OK;
 }
