@@ -75,8 +75,17 @@ constexpr long long F_CACHED_BYTES = 256ll << 20;
 struct PartLayout {
     long long dF, e, sup, a, b;               // m each (one per edge)
     long long dY, p, conj, rnum, rden, nonpos, yinf;  // nblk_node each
+    long long red;                            // CTRL_NQ * CTRL_GROUPS: first-level sums of the control
     long long total;
 };
+
+// The control launch reduces CTRL_NQ partial segments.  When the longest one has more than
+// CTRL_SPLIT_MIN entries, a first launch of CTRL_GROUPS workgroups sums fixed consecutive ranges
+// of every segment (CTRL_GROUPS values each), and the control's single workgroup adds those: a
+// single workgroup alone reads config4's 400,000 node partials per quantity in 0.7 ms.
+constexpr int CTRL_NQ = 12;
+constexpr int CTRL_GROUPS = 256;
+constexpr long long CTRL_SPLIT_MIN = 8192;
 
 // Device buffers of one instance.  In fused mode F, Y and mu ping-pong with F2, Y2,
 // mu2: iteration k reads the buffers of parity (k + parity offset) & 1 and writes the others.

@@ -438,8 +438,14 @@ __device__ __forceinline__ double below(double x, double) { return x; }
 // The new columns of the edges leaving t are added, in edge order and in the iterate type,
 // into Sout[:,t], the out-edge half of P' = F A^T.  (In FP32 that sum of the few columns
 // leaving a node carries rounding of the same order as the FP32 columns themselves.)
+// The partial and check variants of the 8-wave shapes whose regular variant fits 4 waves per SIMD
+// (up to 6 vectors per lane) are held to 128 VGPRs too, so that they also keep 2 workgroups per CU:
+// left alone the FP32 6-vector ones take 130 and 146 and fit one.  Held, the partial one spills 1
+// register and runs 2.30 ms instead of 3.20 at n = 1e4, and the check one spills 19 and runs
+// 4.69 ms instead of 4.71.
 template <typename T, int WPE, int NV, bool CHECK, bool PARTIAL>
-__global__ __launch_bounds__(WPE == 1 ? 256 : 64 * WPE) void edge_kernel(Consts c, Bufs<T> b, PartLayout pl)
+__global__ __launch_bounds__(WPE == 1 ? 256 : 64 * WPE)
+__attribute__((amdgpu_waves_per_eu(WPE == 8 && NV <= 6 && (CHECK || PARTIAL) ? 4 : 1))) void edge_kernel(Consts c, Bufs<T> b, PartLayout pl)
 {
     constexpr int VEC = Vec<T>::N;
     constexpr int LANES = 64 * WPE;  // threads per tail node
@@ -1451,31 +1457,38 @@ __global__ __launch_bounds__(64 * RES_EDGES) void residual_kernel(Consts c, Bufs
 
 // ----------------------------------------------------------------- control
 constexpr int CTRL_BLOCK = 512;
-constexpr int NQ = 12;  // reduced quantities
+constexpr int NQ = CTRL_NQ;  // reduced quantities
 
-// One thread-strided pass over every partial segment with all loads independent, then
-// one block combine: wave sums, and the CTRL_BLOCK/64 wave totals added in wave order.
-// Run by one CTRL_BLOCK-thread block; `lds` holds NQ * CTRL_BLOCK/64 doubles.
-template <typename T>
-__device__ __forceinline__ void control_body(const Consts &c, const Bufs<T> &b, const PartLayout &pl, int check,
-                                             int adapt, long long k_after, double *lds)
+// The partial segments of the control and their lengths (dF and dY first: a control without a
+// check reduces only those two).
+__device__ __forceinline__ void control_segments(const Consts &c, const PartLayout &pl, long long (&seg)[NQ],
+                                                 long long (&len)[NQ])
+{
+    const long long s[NQ] = {pl.dF, pl.dY, pl.e, pl.sup, pl.a, pl.b, pl.p, pl.conj, pl.rnum, pl.rden, pl.nonpos,
+                             pl.yinf};
+    const long long l[NQ] = {c.nep, c.nnp, c.nep, c.nep, c.nrp, c.nrp, c.nnp, c.nnp, c.nnp, c.nnp, c.nnp, c.nnp};
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        seg[q] = s[q];
+        len[q] = l[q];
+    }
+}
+
+// Sums, over the CTRL_BLOCK threads of a workgroup, the entries x0 <= x < x1 of the first nq
+// segments (each only up to its length): one thread-strided pass with all loads independent, then
+// wave sums and the CTRL_BLOCK/64 wave totals added in wave order.  `lds` holds NQ * CTRL_BLOCK/64
+// doubles; the totals are valid in thread 0.
+__device__ __forceinline__ void block_sums(const double *P, const long long (&seg)[NQ], const long long (&len)[NQ],
+                                           int nq, long long x0, long long x1, double (&tot)[NQ], double *lds)
 {
     constexpr int NW = CTRL_BLOCK / 64;
-    DevScalars *sc = b.sc;
-    const double *P = b.part;
-    const long long seg[NQ] = {pl.dF, pl.dY, pl.e, pl.sup, pl.a, pl.b, pl.p, pl.conj, pl.rnum, pl.rden, pl.nonpos,
-                               pl.yinf};
-    const long long len[NQ] = {c.nep, c.nnp, c.nep, c.nep, c.nrp, c.nrp, c.nnp, c.nnp, c.nnp, c.nnp, c.nnp, c.nnp};
-    const int nq = check ? NQ : 2;
     double acc[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
-    long long most = 0;
-    for (int q = 0; q < nq; ++q) most = len[q] > most ? len[q] : most;
     // every load is unconditional (an index past its segment reads the segment's first entry,
     // which is then discarded), so that the NQ loads of a pass are in flight together
 #pragma unroll 2
-    for (long long x = threadIdx.x; x < most; x += CTRL_BLOCK) {
+    for (long long x = x0 + threadIdx.x; x < x1; x += CTRL_BLOCK) {
         double v[NQ];
 #pragma unroll
         for (int q = 0; q < NQ; ++q) v[q] = P[seg[q] + (x < len[q] ? x : 0)];
@@ -1489,14 +1502,57 @@ __device__ __forceinline__ void control_body(const Consts &c, const Bufs<T> &b, 
         if (lane == 0) lds[q * NW + wid] = t;
     }
     __syncthreads();
-    if (threadIdx.x != 0) return;
-    double tot[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
         double t = 0.0;
         for (int w = 0; w < NW; ++w) t += lds[q * NW + w];
         tot[q] = t;
     }
+}
+
+// First level of a split control reduction: workgroup g sums entries [g * chunk, (g + 1) * chunk)
+// of every segment into red[q * CTRL_GROUPS + g], chunk = ceil(longest / CTRL_GROUPS).
+template <typename T>
+__global__ __launch_bounds__(CTRL_BLOCK) void control_split_kernel(Consts c, Bufs<T> b, PartLayout pl, int check)
+{
+    __shared__ double lds[NQ * (CTRL_BLOCK / 64)];
+    if (b.sc->stop) return;
+    long long seg[NQ], len[NQ];
+    control_segments(c, pl, seg, len);
+    const int nq = check ? NQ : 2;
+    long long most = 0;
+    for (int q = 0; q < nq; ++q) most = len[q] > most ? len[q] : most;
+    const long long chunk = (most + CTRL_GROUPS - 1) / CTRL_GROUPS;
+    const long long x0 = (long long)blockIdx.x * chunk, x1 = x0 + chunk < most ? x0 + chunk : most;
+    double tot[NQ];
+    block_sums(b.part, seg, len, nq, x0, x1, tot, lds);
+    if (threadIdx.x == 0)
+        for (int q = 0; q < nq; ++q) b.part[pl.red + (long long)q * CTRL_GROUPS + blockIdx.x] = tot[q];
+}
+
+// The control: totals of the partial segments (or, with `split`, of the first-level sums that
+// control_split_kernel left), then the residuals, the stop test and the primal weight.  Run by
+// one CTRL_BLOCK-thread block; `lds` holds NQ * CTRL_BLOCK/64 doubles.
+template <typename T>
+__device__ __forceinline__ void control_body(const Consts &c, const Bufs<T> &b, const PartLayout &pl, int check,
+                                             int adapt, long long k_after, double *lds, bool split = false)
+{
+    DevScalars *sc = b.sc;
+    long long seg[NQ], len[NQ];
+    control_segments(c, pl, seg, len);
+    if (split) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            seg[q] = pl.red + (long long)q * CTRL_GROUPS;
+            len[q] = CTRL_GROUPS;
+        }
+    }
+    const int nq = check ? NQ : 2;
+    long long most = 0;
+    for (int q = 0; q < nq; ++q) most = len[q] > most ? len[q] : most;
+    double tot[NQ];
+    block_sums(b.part, seg, len, nq, 0, most, tot, lds);
+    if (threadIdx.x != 0) return;
     const double dF2 = tot[0], dY2 = tot[1], e = tot[2], sup = tot[3], a = tot[4], bb = tot[5], psum = tot[6],
                  conj = tot[7], rnum = tot[8], rden = tot[9], nonpos = tot[10], yinf = tot[11];
     const double dF = sqrt(dF2), dY = sqrt(dY2);
@@ -1561,12 +1617,12 @@ __device__ __forceinline__ void control_body(const Consts &c, const Bufs<T> &b, 
 // only thread 0 writes it back after them).
 template <typename T>
 __global__ __launch_bounds__(CTRL_BLOCK) void control_kernel(Consts c, Bufs<T> b, PartLayout pl, int check,
-                                                              int adapt, long long k_inc)
+                                                              int adapt, long long k_inc, int split)
 {
     __shared__ double lds[NQ * (CTRL_BLOCK / 64)];
     if (b.sc->stop) return;
     const long long k_after = b.sc->k + k_inc;
-    control_body<T>(c, b, pl, check, adapt, k_after, lds);
+    control_body<T>(c, b, pl, check, adapt, k_after, lds, split != 0);
 }
 
 template <typename T>
@@ -2003,8 +2059,15 @@ template <typename T>
 hipError_t launch_control(const Consts &c, const Bufs<T> &b, const PartLayout &pl, bool check, bool adapt,
                           long long k_inc, hipStream_t st)
 {
+    // the longest segment the control reads (dF and dY only without a check)
+    const long long most = check ? std::max(std::max((long long)c.nep, (long long)c.nnp), (long long)c.nrp)
+                                 : std::max((long long)c.nep, (long long)c.nnp);
+    const int split = most > CTRL_SPLIT_MIN ? 1 : 0;
+    if (split)
+        hipLaunchKernelGGL(control_split_kernel<T>, dim3(CTRL_GROUPS), dim3(CTRL_BLOCK), 0, st, c, b, pl,
+                           check ? 1 : 0);
     hipLaunchKernelGGL(control_kernel<T>, dim3(1), dim3(CTRL_BLOCK), 0, st, c, b, pl, check ? 1 : 0, adapt ? 1 : 0,
-                       k_inc);
+                       k_inc, split);
     return hipGetLastError();
 }
 

@@ -81,6 +81,7 @@ PartLayout part_layout(int m, int nb)
     p.rden = o; o += nb;
     p.nonpos = o; o += nb;
     p.yinf = o; o += nb;
+    p.red = o; o += (long long)CTRL_NQ * CTRL_GROUPS;
     p.total = o;
     return p;
 }
