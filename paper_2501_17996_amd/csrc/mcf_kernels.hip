@@ -1265,7 +1265,9 @@ __device__ __forceinline__ void fused_body(const Consts &c, const Bufs<T> &b, co
                 if (CHECK) tacc[jj] += (double)(out ? fh : -fh);  // T = -Fhat A^T
                 if (out) {
                     const T fn = rhot * fh + omrt * fo[jj];
-                    Fn[(long long)e * ld + i] = fn;
+                    // non-temporal: this launch reads F (both ends' loads) only from the other
+                    // buffer, so the new column need not take cache room from them
+                    __builtin_nontemporal_store(fn, Fn + (long long)e * ld + i);
                     if (PARTIAL) {
                         const double d = (double)fn - (double)fo[jj];
                         dsum += d * d;
