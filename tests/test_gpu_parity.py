@@ -329,6 +329,28 @@ def _checkpoints(M, inst, mode, ks, precision=0):
     return S
 
 
+@pytest.mark.parametrize("case", range(12))
+def test_random_instances_match_oracle(M, case):
+    """Seeded random draws over the inputs the boundary accepts: n from 3 to 700, out-degree 1 to
+    12, log, power (gamma in (0.1, 0.9)) and alpha-fair (alpha 0.5, 2 or 3) utilities, capacity and
+    weight ranges of one decade placed anywhere in [0.1, 10], parallel edges on every third draw;
+    the automatic kernel choice on even cases and the two-phase iteration forced on odd ones.  FP64
+    state and check metrics against the oracle at k = 1, 7 and 40."""
+    rng = np.random.default_rng(9000 + case)
+    n = int(rng.integers(3, 701))
+    deg = int(rng.integers(1, min(12, n - 1) + 1))
+    kind = int(rng.integers(0, 3))
+    utility = (I.UTIL_LOG, I.UTIL_POWER, I.UTIL_ALPHA)[kind]
+    gamma = (0.5, float(rng.uniform(0.1, 0.9)), float(rng.choice([0.5, 2.0, 3.0])))[kind]
+    c0, w0 = 10.0 ** rng.uniform(-1.0, 0.0), 10.0 ** rng.uniform(-1.0, 0.0)
+    inst = I.ring_instance(n, deg, seed=9100 + case, utility=utility, gamma=gamma, cap_range=(c0, 10 * c0),
+                           w_range=(w0, 10 * w0))
+    if case % 3 == 0:
+        inst = I.with_parallel_edges(inst, max(1, inst.m // 10), seed=9200 + case)
+    print(f"random case {case}: n={n} m={inst.m} utility={utility} gamma={gamma:.3f} mode={case % 2}", flush=True)
+    _checkpoints(M, inst, case % 2, (1, 7, 40))
+
+
 @pytest.mark.parametrize("mode", [0, 1])
 def test_parallel_edges_trajectory(M, mode):
     """Parallel edges (allowed by the boundary): each copy is its own column of F, and each
