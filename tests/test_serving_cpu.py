@@ -1,9 +1,11 @@
 """Serving-loop bookkeeping on a CPU stand-in backend: admission by slots and
 memory footprint, continuous batching, retirement, latency percentiles."""
 import numpy as np
+from hypothesis import given, settings
+from hypothesis import strategies as hst
 
 from paper_2501_17996_amd import instances as I
-from paper_2501_17996_amd.serve import Arena, Request, percentile, serve
+from paper_2501_17996_amd.serve import ALIGN, Arena, Request, percentile, serve
 from tests.fake_backend import OracleBackend
 
 
@@ -132,3 +134,34 @@ def test_serving_loop_keeps_one_step_in_flight_while_host_works():
     assert creates[:2] == ["create:idle", "create:idle"] and set(creates[2:]) == {"create:busy"}
     # every destroy but those after the last step overlaps a step
     assert destroys.count("destroy:busy") >= len(destroys) - 2
+
+
+@settings(max_examples=30, deadline=None)
+@given(sizes=hst.lists(hst.tuples(hst.integers(3, 12), hst.floats(0.0, 0.005)), min_size=1, max_size=10),
+       slots=hst.integers(1, 4), budget=hst.integers(1500, 30000), refuse=hst.sets(hst.integers(3, 12), max_size=2),
+       max_n=hst.integers(3, 12))
+def test_serving_invariants_on_random_streams(sizes, slots, budget, refuse, max_n):
+    """Random streams (sizes, arrival gaps), slot counts, arena sizes, sizes the backend cannot batch
+    and sizes whose admission fails: every request is answered exactly once, rejected exactly when
+    its footprint exceeds the arena, its size is not batched or its admission fails, and otherwise
+    solved; slots and memory are never oversubscribed, and every block and handle is returned."""
+    reqs, t = [], 0.0
+    for r, (n, gap) in enumerate(sizes):
+        t += gap
+        reqs.append(Request(r, t, I.ring_instance(n, min(2, n - 1), seed=500 + r)))
+    be = OracleBackend(budget=budget, max_slots=slots, check_every=10, tol=1e-3, max_iter=300, max_n=max_n,
+                       refuse_admit=refuse)
+    fp = {q.rid: q.inst.n * q.inst.m * be.bpv for q in reqs}
+    nn = {q.rid: q.inst.n for q in reqs}
+    records, summary = serve(reqs, be)
+    assert sorted(r.rid for r in records) == list(range(len(reqs)))
+    for r in records:
+        too_big = (fp[r.rid] + ALIGN - 1) // ALIGN * ALIGN > budget
+        should_reject = too_big or nn[r.rid] > max_n or nn[r.rid] in refuse
+        assert (r.state == "rejected") == should_reject, (r.rid, r.state, too_big, nn[r.rid])
+        if r.state != "rejected":
+            assert r.state in ("converged", "max_iter")
+            assert r.arrival <= r.admitted <= r.done
+    assert summary["requests"] + summary["rejected"] == len(reqs)
+    assert be.peak_slots <= slots and be.peak_bytes <= budget
+    assert be.arena.free == [(0, be.arena.size)] and be.live == 0
